@@ -1,0 +1,32 @@
+"""FP64 CPU oracle for the edge-partitioned kernel path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this
+package: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library and imports nothing
+from it; the two meet only in the seeded input generators (package ``gen``).
+
+Each function is a plain, slow, obviously-correct statement of what the method
+computes, written from the paper (arXiv 1605.02043, "A Graph-based Model for
+GPU Caching Problems"):
+
+* ``graph``   - data-affinity graph, clone-and-connect transform, reconstruction
+                (Definitions 1, 3, 4).
+* ``cost``    - partition cost C, loads L and friends (Definition 2, Eq. 1).
+* ``ggp``     - the balanced vertex partition of the transformed graph, read as a
+                deterministic greedy graph-growing partitioner (Section 3.2; the
+                paper uses METIS, which is absent).
+* ``cpack``   - first-touch data packing along the task order (Section 4.1).
+* ``flux``    - the cfd-style pairwise interaction, forward and adjoint (the
+                paper names the interaction's inputs in Section 3.1 but gives no
+                formula; the formula here is this project's reading).
+* ``spmv``    - y_i += w * x_j over the bipartite SpMV graph (Section 5.2).
+* ``brute``   - exhaustive optimal partitions for tiny graphs (Theorems 1-2).
+
+Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
+by closed forms, invariants, textbook properties and library routines in the
+CPU tests.  The exact output of ``ggp.partition`` and ``cpack.layout`` beyond
+those pins is parity unpinned: it is fixed by their specification and checked
+only by two independent implementations agreeing bit for bit.
+"""
+
+from . import graph, cost, ggp, cpack, flux, spmv, brute  # noqa: F401

@@ -1,0 +1,295 @@
+"""Pins for the oracle's partition side: Definitions 1-4, Eq. 1, Theorems 1-2,
+Figure 1 / Figure 3, closed forms and brute force on tiny graphs."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from oracle import brute, cost, cpack, ggp, graph
+
+
+def _fig1(golden_dir):
+    with open(os.path.join(golden_dir, "fig1.json")) as f:
+        return json.load(f)
+
+
+def _fetched_twice(edges, n, part):
+    return cost.partition_cost(edges, n, part)["replicated"]
+
+
+# ---------------------------------------------------------------- Figure 1 / 3
+
+def test_fig1_default_schedule_loads(golden_dir):
+    G = _fig1(golden_dir)
+    E, n, T = np.array(G["edges"]), G["n"], G["threads_per_block"]
+    part = np.arange(len(E)) // T  # consecutive tasks per block
+    assert part.tolist() == G["default_parts"]
+    c = cost.partition_cost(E, n, part)
+    assert c["loads"] == G["default_loads"] == 9
+    assert cost.loads_simple(E, part) == 9
+    assert _fetched_twice(E, n, part) == G["default_fetched_twice"] == 3
+
+
+def test_fig1_ep_schedule_loads(golden_dir):
+    G = _fig1(golden_dir)
+    E, n = np.array(G["edges"]), G["n"]
+    c = cost.partition_cost(E, n, G["ep_parts"])
+    assert c["loads"] == G["ep_loads"] == 7
+    assert c["cost"] == G["optimal_cost"] == 1
+    assert _fetched_twice(E, n, G["ep_parts"]) == G["ep_fetched_twice"] == 1
+    # the particle shared by e1, e2, e4 lands in one block only
+    assert c["p_v"][G["ep_shared_by_e1_e2_e4_loaded_once"]] == 1
+
+
+def test_fig1_brute_force_optimum(golden_dir):
+    G = _fig1(golden_dir)
+    E, n = np.array(G["edges"]), G["n"]
+    best, _ = brute.min_edge_partition_cost(E, n, G["threads_per_block"])
+    assert best == G["optimal_cost"]
+
+
+def test_fig1_ggp_finds_the_ep_schedule(golden_dir):
+    G = _fig1(golden_dir)
+    E, n = np.array(G["edges"]), G["n"]
+    part, task = ggp.partition(E, n, G["threads_per_block"])
+    assert part.tolist() == G["ep_parts"]
+    assert task.tolist() == [0, 1, 3, 2, 4, 5]
+    assert cost.partition_cost(E, n, part)["loads"] == 7
+
+
+# ---------------------------------------------------------------- Definition 3 counts
+
+def _random_graph(rng, n, m, allow_dup=True):
+    E = []
+    while len(E) < m:
+        u, v = rng.integers(0, n, 2)
+        if u == v:
+            continue
+        if not allow_dup and (min(u, v), max(u, v)) in {(min(a, b), max(a, b)) for a, b in E}:
+            continue
+        E.append((int(u), int(v)))
+    return np.array(E, dtype=np.int64).reshape(-1, 2)
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(2, 12), st.integers(1, 30), st.integers(0, 10_000))
+def test_transform_counts(n, m, seed):
+    E = _random_graph(np.random.default_rng(seed), n, m)
+    D = graph.clone_and_connect(E, n)
+    deg = np.bincount(E.ravel(), minlength=n)
+    n_active = int((deg > 0).sum())
+    assert D["n_clones"] == 2 * m  # |V'| = 2m
+    assert len(D["aux"]) == int((deg[deg > 0] - 1).sum()) == 2 * m - n_active
+    # every clone is on exactly one original edge
+    on = np.zeros(2 * m, dtype=int)
+    for a, b in D["original"]:
+        on[a] += 1
+        on[b] += 1
+    assert (on == 1).all()
+    # the clones of each vertex form a path: degree <= 2 in the aux graph, d-1 links
+    adeg = np.zeros(2 * m, dtype=int)
+    for a, b in D["aux"]:
+        assert D["owner"][a] == D["owner"][b]
+        adeg[a] += 1
+        adeg[b] += 1
+    assert adeg.max(initial=0) <= 2
+    # contracted links are the aux edges seen from each contracted node
+    nbr = graph.contracted_links(E, n)
+    assert sum(len(x) for x in nbr) == 2 * len(D["aux"])
+
+
+def test_reconstruct_rejects_cut_original_edge():
+    E = np.array([[0, 1], [1, 2]])
+    D = graph.clone_and_connect(E, 3)
+    with pytest.raises(ValueError):
+        graph.reconstruct(D, [0, 1, 0, 0])
+    assert graph.reconstruct(D, [1, 1, 0, 0]).tolist() == [1, 0]
+
+
+# ---------------------------------------------------------------- invariants of the partitioner
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(2, 40), st.integers(1, 120), st.integers(1, 17), st.integers(0, 10_000))
+def test_ggp_invariants(n, m, cap, seed):
+    E = _random_graph(np.random.default_rng(seed), n, m)
+    part, task = ggp.partition(E, n, cap)
+    k = math.ceil(m / cap)
+    assert sorted(task.tolist()) == list(range(m))  # every edge placed exactly once
+    sizes = np.bincount(part, minlength=k)
+    assert len(sizes) == k and part.min() == 0 and part.max() == k - 1
+    assert (sizes[:-1] == cap).all() and 1 <= sizes[-1] <= cap
+    # task order visits the parts in ascending id
+    assert (np.diff(part[task]) >= 0).all()
+    c = cost.partition_cost(E, n, part, k)
+    assert c["loads"] == c["cost"] + c["n_active"]
+    assert c["slots"] == c["cost"] + c["replicated"]
+    assert c["loads"] == cost.loads_simple(E, part)
+    # Theorem 1: cut auxiliary edges bound the vertex-cut cost
+    assert c["cost"] <= c["aux_cut"]
+    D = graph.clone_and_connect(E, n)
+    assert graph.vertex_cut(D, np.repeat(part, 2)) == c["aux_cut"]
+    # the layout's per-part vertex lists add up to the loads
+    lay = cpack.layout(E, n, part, task)
+    assert sum(info["nown"][0] + len(info["foreign"][0]) for info in lay["parts"]) == c["loads"]
+    assert sum(len(info["foreign"][0]) for info in lay["parts"]) == c["cost"]
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(2, 30), st.integers(1, 80), st.integers(1, 9), st.integers(0, 10_000))
+def test_theorem2_rechained_transform_is_exact(n, m, cap, seed):
+    """Regrouping each vertex's clones by part makes the aux cut equal C."""
+    E = _random_graph(np.random.default_rng(seed), n, m)
+    for part in (ggp.partition(E, n, cap)[0], np.arange(m) // cap,
+                 np.random.default_rng(seed + 1).integers(0, math.ceil(m / cap), m)):
+        D2 = graph.rechain_by_part(E, n, part)
+        assert graph.vertex_cut(D2, np.repeat(part, 2)) == cost.partition_cost(E, n, part)["cost"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_bounds(seed):
+    """C* <= C(GGP); C* <= C(recon(VP*)) <= cut(VP*) <= (d_max - 1) C*  (Theorems 1-2)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 7))
+    m = int(rng.integers(3, 9))
+    cap = int(rng.integers(2, 5))
+    E = _random_graph(rng, n, m)
+    c_star, _ = brute.min_edge_partition_cost(E, n, cap)
+    cut_star, vp_part = brute.min_vertex_partition_cut(E, n, cap)
+    c_recon = cost.partition_cost(E, n, vp_part)["cost"]
+    d_max = int(np.bincount(E.ravel()).max())
+    assert c_star <= c_recon <= cut_star <= max(d_max - 1, 1) * c_star or (c_star == 0 and cut_star == 0)
+    part, _ = ggp.partition(E, n, cap)
+    assert cost.partition_cost(E, n, part)["cost"] >= c_star
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("m,cap", [(1, 1), (10, 3), (64, 8), (65, 8), (200, 16)])
+def test_path_closed_form(m, cap):
+    E = np.stack([np.arange(m), np.arange(1, m + 1)], axis=1)
+    k = math.ceil(m / cap)
+    part, _ = ggp.partition(E, m + 1, cap)
+    assert cost.partition_cost(E, m + 1, part)["cost"] == k - 1
+    if m <= 9:
+        assert brute.min_edge_partition_cost(E, m + 1, cap)[0] == k - 1
+
+
+@pytest.mark.parametrize("m,cap", [(1, 1), (9, 4), (30, 7), (100, 10)])
+def test_star_closed_form(m, cap):
+    E = np.stack([np.zeros(m, dtype=int), np.arange(1, m + 1)], axis=1)
+    k = math.ceil(m / cap)
+    rng = np.random.default_rng(m)
+    for part in (ggp.partition(E, m + 1, cap)[0], np.arange(m) // cap, rng.permutation(np.arange(m) // cap)):
+        assert cost.partition_cost(E, m + 1, part)["cost"] == k - 1
+
+
+@pytest.mark.parametrize("m,cap", [(6, 3), (8, 2), (9, 4)])
+def test_cycle_closed_form(m, cap):
+    E = np.stack([np.arange(m), (np.arange(m) + 1) % m], axis=1)
+    k = math.ceil(m / cap)
+    assert brute.min_edge_partition_cost(E, m, cap)[0] == k
+    part, _ = ggp.partition(E, m, cap)
+    assert cost.partition_cost(E, m, part)["cost"] >= k
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_disjoint_components_reach_zero(seed):
+    cap = 6
+    rng = np.random.default_rng(seed)
+    comps = []
+    base = 0
+    for _ in range(7):  # components of exactly cap edges: paths, stars, a triangle fan
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            comps.append(np.stack([np.arange(cap), np.arange(1, cap + 1)], 1) + base)
+            base += cap + 1
+        elif kind == 1:
+            comps.append(np.stack([np.zeros(cap, int), np.arange(1, cap + 1)], 1) + base)
+            base += cap + 1
+        else:
+            comps.append(np.array([[0, 1], [1, 2], [0, 2], [2, 3], [0, 3], [3, 4]]) + base)
+            base += 5
+    E = np.concatenate(comps)
+    ids = rng.permutation(base)
+    E = ids[E]
+    E = E[rng.permutation(len(E))]
+    part, _ = ggp.partition(E, base, cap)
+    assert cost.partition_cost(E, base, part)["cost"] == 0
+
+
+@settings(max_examples=30, deadline=None)
+@given(st.integers(1, 60), st.integers(1, 10), st.integers(0, 1000))
+def test_max_degree_two_aux_cut_equals_cost(m, cap, seed):
+    """Disjoint paths and cycles (d_max <= 2): every cut chain link is a split vertex."""
+    rng = np.random.default_rng(seed)
+    n = 2 * m + 2
+    ids = rng.permutation(n)
+    E = []
+    v = 0
+    while len(E) < m:
+        L = int(rng.integers(1, 8))
+        L = min(L, m - len(E))
+        for t in range(L):
+            E.append((ids[v + t], ids[v + t + 1]))
+        v += L + 1
+    E = np.array(E)
+    E = E[rng.permutation(len(E))]
+    for part in (ggp.partition(E, n, cap)[0], rng.integers(0, math.ceil(m / cap), m)):
+        c = cost.partition_cost(E, n, part)
+        assert c["aux_cut"] == c["cost"]
+
+
+def test_input_order_is_consecutive_blocks():
+    E = _random_graph(np.random.default_rng(3), 20, 50)
+    part, task = ggp.partition(E, 20, 7, order="input")
+    assert part.tolist() == (np.arange(50) // 7).tolist()
+    assert task.tolist() == list(range(50))
+
+
+# ---------------------------------------------------------------- cpack
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(2, 40), st.integers(1, 100), st.integers(1, 13), st.integers(0, 1000))
+def test_cpack_layout(n, m, cap, seed):
+    E = _random_graph(np.random.default_rng(seed), n, m)
+    part, task = ggp.partition(E, n, cap)
+    lay = cpack.layout(E, n, part, task)
+    perm = lay["perm"]
+    assert sorted(perm.tolist()) == list(range(n))
+    assert (lay["orig_to_packed"][perm] == np.arange(n)).all()
+    # first-touch order along the task sequence
+    seen, expect = set(), []
+    for e in task:
+        for w in E[e]:
+            if int(w) not in seen:
+                seen.add(int(w))
+                expect.append(int(w))
+    iso = sorted(set(range(n)) - seen)
+    assert perm.tolist() == expect + iso
+    # owned ranges tile [0, n_active) in part order
+    cur = 0
+    for info in lay["parts"]:
+        assert info["own0"][0] == cur
+        cur += info["nown"][0]
+        f = info["foreign"][0]
+        assert (np.diff(f) > 0).all() if len(f) > 1 else True
+        assert (f < info["own0"][0]).all()  # foreign vertices were packed by earlier parts
+    assert cur == n - len(iso)
+
+
+def test_cpack_bipartite_classes():
+    rng = np.random.default_rng(7)
+    n_x, n_y = 30, 20
+    m = 90
+    E = np.stack([rng.integers(0, n_x, m), n_x + rng.integers(0, n_y, m)], 1)
+    part, task = ggp.partition(E, n_x + n_y, 8)
+    lay = cpack.layout(E, n_x + n_y, part, task, n_x=n_x)
+    o2p = lay["orig_to_packed"]
+    assert (o2p[:n_x] < n_x).all() and (o2p[n_x:] >= n_x).all()
+    c = cost.partition_cost(E, n_x + n_y, part)
+    tot = sum(info["nown"][cl] + len(info["foreign"][cl]) for info in lay["parts"] for cl in (0, 1))
+    assert tot == c["loads"]
