@@ -1,0 +1,191 @@
+/*
+ * epk.h - edge-partitioned kernels for MI355X (gfx950).
+ *
+ * C ABI of libepk, an implementation of the edge-centric data-affinity model of
+ * "A Graph-based Model for GPU Caching Problems" (arXiv 1605.02043):
+ *
+ *   - a data object is a vertex and a task is an edge using two objects
+ *     (Section 3.1, Definition 1);
+ *   - tasks are grouped into workgroups by a balanced edge partition that
+ *     minimises the vertex-cut cost C = sum_v (p_v - 1), the number of
+ *     redundant loads (Section 3.1, Definition 2, Eq. 1), solved through the
+ *     clone-and-connect transform and a balanced vertex partition
+ *     (Section 3.2, Definitions 3-4);
+ *   - data are repacked along the new task order and every workgroup stages
+ *     its distinct vertices in on-chip memory with coalesced loads
+ *     (Section 4, Section 4.1).
+ *
+ * Conventions (every function):
+ *   - Return value: an epk_status; EPK_OK is 0, errors are negative.  After a
+ *     non-OK status, epk_last_error() returns a message (thread-local).
+ *   - Host arrays passed in are owned by the caller and only read during the
+ *     call; the library copies what it keeps.
+ *   - Device pointers are borrowed: the caller allocates and frees them.  The
+ *     library never allocates device memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device functions enqueue work on that stream and return without
+ *     synchronising; validation of every argument happens before any launch.
+ *   - Vertex ids are int32, counts int64.  Vertex state is row-major
+ *     [n][5] float32 (rho, m1, m2, m3, E), indexed by PACKED vertex id.
+ *   - Nothing here aborts or throws across the ABI.
+ *   - A plan may be used from several streams at once only with distinct
+ *     workspaces and outputs.
+ */
+#ifndef EPK_H
+#define EPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EPK_OK = 0,
+  EPK_EINVAL = -1, /* null pointer, vertex id out of range, self-loop, cap < 1, bad enum */
+  EPK_ERANGE = -2, /* sizes beyond what the kernels support (LDS budget, 16-bit local ids) */
+  EPK_EHIP = -3,   /* HIP runtime or launch error */
+  EPK_ESTATE = -4, /* plan/batch not uploaded, or used with the wrong kind */
+  EPK_ENOMEM = -5  /* host allocation failed */
+} epk_status;
+
+typedef enum {
+  EPK_ORDER_EP = 0,   /* edge partition through the transformed graph (Section 3.2) */
+  EPK_ORDER_INPUT = 1 /* default schedule: consecutive tasks per block, part = e / cap (Section 1) */
+} epk_order;
+
+typedef enum {
+  EPK_FLUX5 = 0, /* cfd-style pairwise interaction on 5-component states */
+  EPK_SPMV = 1   /* y_i += w_e x_j on the bipartite SpMV graph (Section 5.2) */
+} epk_kind;
+
+/* Partition quality and overhead (Definition 2; Section 3.2 balance factor).
+ * loads L = sum_i |V(P_i)|, cost C = L - n_active, replicated R = #{p_v >= 2},
+ * slots S = sum_{p_v >= 2} p_v, aux_cut = cut auxiliary edges of the
+ * index-order transform, balance = max part size / (m / k).              */
+typedef struct {
+  int64_t n_parts, loads, cost, replicated, slots, aux_cut, n_active;
+  int64_t max_part_edges, max_part_vertices;
+  double balance, partition_seconds, plan_seconds;
+} epk_stats;
+
+/* A data-affinity graph (Definition 1).
+ * FLUX5: edge e = (u, v), geometry = the unit normal from u to v (+ area):
+ *        geom_ncomp 2 -> (nx, ny), area 1;  4 -> (nx, ny, nz, area).
+ * SPMV : vertices [0, n_x) are x, [n_x, n_vertices) are y; edge e must be
+ *        (j, n_x + i) for nonzero A[i][j]; geom_ncomp 1 -> the weight A[i][j].
+ * edge_uv is host [n_edges][2], edge_geom host [n_edges][geom_ncomp].      */
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_x; /* SPMV only; 0 for FLUX5 */
+  int64_t n_edges;
+  const int32_t *edge_uv;
+  const float *edge_geom;
+  int32_t geom_ncomp;
+} epk_graph;
+
+typedef struct epk_plan epk_plan;
+typedef struct epk_batch epk_batch;
+
+/* ------------------------------------------------------------------ host */
+
+/* The paper's problem (Eq. 1): graph + capacity in, edge -> part and cost out.
+ * k = ceil(m / capacity); parts 0..k-2 hold exactly `capacity` edges.
+ * part_of_edge[m] and task_order[m] are caller-allocated (task_order may be
+ * NULL): task_order lists the edges part by part, in placement order.
+ * Host only, synchronous; geometry is not read.                          */
+int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *part_of_edge,
+                  int32_t *task_order, epk_stats *stats);
+
+/* Plan = partition + data packing along the task order (Section 4.1) + the
+ * device image the kernels read.  Host only, synchronous.                */
+int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind, epk_plan **out);
+/* Bytes of the device image and of the per-call workspace (replicated-vertex
+ * partials).  Both are caller-allocated; alignment 256 bytes.             */
+int epk_plan_device_bytes(const epk_plan *p, size_t *image_bytes, size_t *workspace_bytes);
+/* Copy the image to d_image (borrowed for the plan's lifetime) on stream. */
+int epk_plan_upload(epk_plan *p, void *d_image, void *stream);
+/* packed_to_orig[n]: original id of each packed vertex id.               */
+int epk_plan_vertex_perm(const epk_plan *p, int32_t *packed_to_orig);
+/* part_of_edge[m], task_order[m] as epk_partition returns them.          */
+int epk_plan_part_of_edge(const epk_plan *p, int32_t *part_of_edge, int32_t *task_order);
+/* Per part and vertex class (FLUX5: 1 class; SPMV: x then y, 2 classes):
+ * own_begin/own_count[k * ncls] = the contiguous packed range the part owns
+ * (its first-touched vertices); foreign_offset[k * ncls + 1] and
+ * foreign_ids[cost] = the packed ids of the part's other vertices,
+ * ascending.  Any pointer may be NULL.                                    */
+int epk_plan_layout(const epk_plan *p, int32_t *own_begin, int32_t *own_count, int64_t *foreign_offset,
+                    int32_t *foreign_ids);
+int epk_plan_stats(const epk_plan *p, epk_stats *s);
+/* Kernel-side sizes: [0] = n_parts, [1] = dynamic LDS bytes of the forward,
+ * [2] = of the adjoint, [3] = workgroup size, [4] = vertex classes,
+ * [5] = algorithmic HBM bytes of one forward (fwd + reduce),
+ * [6] = algorithmic HBM bytes of one adjoint (bwd + reduce),
+ * [7] = forward-kernel-only bytes, [8] = adjoint-kernel-only bytes.        */
+int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
+/* Launch shape for later calls: workgroup size wg (64..1024, multiple of
+ * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
+ * xcd_swizzle (1: XCD x runs the consecutive parts [x*ceil(k/8),
+ * (x+1)*ceil(k/8)), so parts sharing vertices share an L2; 0: part =
+ * workgroup id; -1 keeps the current one).  Host only.                   */
+int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle);
+void epk_plan_destroy(epk_plan *p);
+
+/* ---------------------------------------------------------------- device */
+
+/* FLUX5 forward on packed states: r = sum of a_e F_e over the incident
+ * edges (+ at u, - at v) and, if q_new != NULL, q_new = q + dt r.
+ * q, r, q_new: device [n][5] float32; d_ws: workspace_bytes.  Each
+ * workgroup stages its part's vertices in LDS, accumulates per-vertex
+ * partials there, writes owned vertices directly and replicated partials to
+ * the workspace; a second kernel sums those in ascending part order.     */
+int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream);
+/* FLUX5 adjoint: g_q = (dr/dq)^T g_r, same partition and reduction.      */
+int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream);
+/* SPMV: y[n_y] = A x[n_x] in packed x / y ids (y packed id - n_x).        */
+int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream);
+/* dst[i] = src[idx[i]] (inverse = 0) or dst[idx[i]] = src[i] (inverse = 1),
+ * rows of ncomp float32; packs states into / out of packed order.         */
+int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp,
+                     int32_t inverse, void *stream);
+
+/* --------------------------------------------------------------- batched */
+
+/* Many FLUX5 graphs in one persistent launch.  States of graph g live at
+ * rows [vertex_offset(g), vertex_offset(g) + n_g) of one [sum n][5] array,
+ * in graph g's packed order.  The plans must be FLUX5 with 4 geometry
+ * components; the batch copies what it needs, the plans may be destroyed.
+ * Work items (graph, part) are taken from a device-side queue in
+ * decreasing size; the queue resets itself at the end of every launch.   */
+int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out);
+int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes);
+/* Copy the image (including a zeroed queue counter) to d_image.          */
+int epk_batch_upload(epk_batch *b, void *d_image, void *stream);
+/* vertex_offset[n_graphs + 1] (rows), total in [n_graphs].               */
+int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset);
+/* [0] items, [1] grid, [2] LDS bytes, [3] algorithmic bytes of one forward. */
+int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info);
+int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream);
+int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws,
+                       void *stream);
+void epk_batch_destroy(epk_batch *b);
+
+/* Capacity selection: for every graph, time the forward at each capacity in
+ * caps[n_caps] and keep the fastest per size class (graphs grouped by
+ * vertex-count decile); results are cached in cache_path (a text file,
+ * NULL = no cache).  d_scratch (scratch_bytes) is caller-allocated device
+ * memory for the trials; EPK_ERANGE if it is too small.  Synchronises the
+ * stream.  chosen_cap[n_graphs] out; chosen_wg may be NULL.               */
+int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps,
+                 const char *cache_path, void *d_scratch, size_t scratch_bytes, void *stream,
+                 int32_t *chosen_cap, int32_t *chosen_wg);
+
+const char *epk_last_error(void);
+const char *epk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPK_H */

@@ -1,0 +1,500 @@
+// Device-side C ABI of libepk: upload, forward, adjoint, SpMV, permutation,
+// batched persistent launch and capacity autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "epk_internal.h"
+#include "kernels.h"
+
+namespace epk {
+
+template <typename T>
+static const T *dptr(void *base, size_t off) {
+  return reinterpret_cast<const T *>(static_cast<uint8_t *>(base) + off);
+}
+
+DevPlan dev_plan(const epk_plan *p) {
+  DevPlan P{};
+  void *b = p->d_image;
+  const ImageLayout &L = p->lay;
+  P.hdr = dptr<int32_t>(b, L.hdr);
+  P.eloc = dptr<uint32_t>(b, L.eloc);
+  P.geom = dptr<float>(b, L.geom);
+  P.inc = dptr<uint16_t>(b, L.inc);
+  P.loff = dptr<uint16_t>(b, L.loff);
+  P.fid = dptr<int32_t>(b, L.fid);
+  P.rvid = dptr<int32_t>(b, L.rvid);
+  P.roff = dptr<int32_t>(b, L.roff);
+  P.rslot = dptr<int32_t>(b, L.rslot);
+  P.heavy = dptr<int32_t>(b, L.heavy);
+  P.items = nullptr;
+  P.iso = nullptr;
+  P.queue = nullptr;
+  P.m = p->m;
+  P.k = int32_t(p->k);
+  P.cap = p->cap;
+  P.geom_ncomp = p->geom_ncomp;
+  P.n = int32_t(p->n_out);
+  P.n_active = int32_t(p->n_active_out);
+  P.R = int32_t(p->R);
+  P.n_heavy = int32_t(p->n_heavy);
+  P.max_u = int32_t(p->max_u);
+  P.max_uy = int32_t(p->max_uy);
+  P.grid = 0;
+  P.n_iso = 0;
+  return P;
+}
+
+DevPlan dev_batch(const epk_batch *bt) {
+  DevPlan P{};
+  void *b = bt->d_image;
+  const ImageLayout &L = bt->lay;
+  P.hdr = dptr<int32_t>(b, L.hdr);
+  P.eloc = dptr<uint32_t>(b, L.eloc);
+  P.geom = dptr<float>(b, L.geom);
+  P.inc = dptr<uint16_t>(b, L.inc);
+  P.loff = dptr<uint16_t>(b, L.loff);
+  P.fid = dptr<int32_t>(b, L.fid);
+  P.rvid = dptr<int32_t>(b, L.rvid);
+  P.roff = dptr<int32_t>(b, L.roff);
+  P.rslot = dptr<int32_t>(b, L.rslot);
+  P.heavy = dptr<int32_t>(b, L.heavy);
+  P.items = dptr<int32_t>(b, L.items);
+  P.iso = dptr<int32_t>(b, L.iso);
+  P.queue = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b) + L.queue);
+  P.m = bt->m;
+  P.k = int32_t(bt->k);
+  P.cap = int32_t(bt->max_cap);
+  P.geom_ncomp = 4;
+  P.n = int32_t(bt->n);
+  P.n_active = int32_t(bt->n);
+  P.R = int32_t(bt->R);
+  P.n_heavy = int32_t(bt->n_heavy);
+  P.max_u = int32_t(bt->max_u);
+  P.max_uy = 0;
+  P.grid = int32_t(bt->grid);
+  P.n_iso = int32_t(bt->n_iso);
+  return P;
+}
+
+static int hip_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return EPK_OK;
+  return fail(EPK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ batch merge
+
+template <typename T>
+static const T *hptr(const epk_plan *p, size_t off) {
+  return reinterpret_cast<const T *>(p->image.data() + off);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out) {
+  if (n_graphs < 1 || !plans) return fail(EPK_EINVAL, "need at least one plan");
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    if (!plans[g]) return fail(EPK_EINVAL, "plan " + std::to_string(g) + " is NULL");
+    if (plans[g]->kind != EPK_FLUX5 || plans[g]->geom_ncomp != 4)
+      return fail(EPK_ESTATE, "batched plans must be FLUX5 with 4 geometry components");
+  }
+  epk_batch *B = new epk_batch();
+  B->n_graphs = n_graphs;
+  B->voff.assign(size_t(n_graphs) + 1, 0);
+  std::vector<int32_t> hdr, fid, rvid, roff(1, 0), rslot, heavy, iso, items;
+  std::vector<uint32_t> eloc;
+  std::vector<float> geom;
+  std::vector<uint16_t> inc, loff;
+  int64_t eoff = 0, foff = 0, lofs_off = 0, rbase = 0;
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    const epk_plan *p = plans[g];
+    const ImageLayout &L = p->lay;
+    const int64_t voff = B->voff[g];
+    const int64_t C = int64_t(p->foreign_ids.size());
+    const int64_t nloff = p->stats.loads + p->k;
+    const int32_t *h = hptr<int32_t>(p, L.hdr);
+    for (int64_t q = 0; q < p->k; ++q) {
+      const int32_t *hq = h + q * kHdrInts;
+      hdr.push_back(int32_t(hq[0] + eoff));
+      hdr.push_back(hq[1]);
+      hdr.push_back(int32_t(hq[2] + voff));
+      hdr.push_back(hq[3]);
+      hdr.push_back(int32_t(hq[4] + foff));
+      hdr.push_back(hq[5]);
+      hdr.push_back(int32_t(hq[6] + lofs_off));
+      hdr.push_back(hq[7]);
+    }
+    eloc.insert(eloc.end(), hptr<uint32_t>(p, L.eloc), hptr<uint32_t>(p, L.eloc) + p->m);
+    geom.insert(geom.end(), hptr<float>(p, L.geom), hptr<float>(p, L.geom) + 4 * p->m);
+    inc.insert(inc.end(), hptr<uint16_t>(p, L.inc), hptr<uint16_t>(p, L.inc) + 2 * p->m);
+    loff.insert(loff.end(), hptr<uint16_t>(p, L.loff), hptr<uint16_t>(p, L.loff) + nloff);
+    for (int64_t i = 0; i < C; ++i) fid.push_back(int32_t(hptr<int32_t>(p, L.fid)[i] + voff));
+    for (int64_t i = 0; i < p->R; ++i) {
+      rvid.push_back(int32_t(hptr<int32_t>(p, L.rvid)[i] + voff));
+      roff.push_back(int32_t(hptr<int32_t>(p, L.roff)[i + 1] + foff));
+    }
+    for (int64_t i = 0; i < C; ++i) rslot.push_back(int32_t(hptr<int32_t>(p, L.rslot)[i] + foff));
+    for (int64_t i = 0; i < p->n_heavy; ++i) heavy.push_back(int32_t(hptr<int32_t>(p, L.heavy)[i] + rbase));
+    for (int64_t v = p->n_active_out; v < p->n_out; ++v) iso.push_back(int32_t(v + voff));
+    B->voff[g + 1] = voff + p->n;
+    B->max_u = std::max<int64_t>(B->max_u, p->max_u);
+    B->max_cap = std::max<int64_t>(B->max_cap, p->cap);
+    B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce;
+    B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce;
+    eoff += p->m;
+    foff += C;
+    lofs_off += nloff;
+    rbase += p->R;
+    B->k += p->k;
+  }
+  B->m = eoff;
+  B->n = B->voff[n_graphs];
+  B->R = rbase;
+  B->n_heavy = int64_t(heavy.size());
+  B->n_iso = int64_t(iso.size());
+  if (B->k >= (int64_t(1) << 31) || B->n >= (int64_t(1) << 31) || B->m >= (int64_t(1) << 31)) {
+    delete B;
+    return fail(EPK_ERANGE, "batch too large for 32-bit ids");
+  }
+  // largest parts first (ties: lower id first)
+  items.resize(size_t(B->k));
+  for (int64_t i = 0; i < B->k; ++i) items[i] = int32_t(i);
+  std::stable_sort(items.begin(), items.end(),
+                   [&](int32_t a, int32_t b) { return hdr[size_t(a) * kHdrInts + 1] > hdr[size_t(b) * kHdrInts + 1]; });
+  B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
+  B->lds_fwd = flux_fwd_lds(B->max_u, B->max_cap);
+  B->lds_bwd = flux_bwd_lds(B->max_u, B->max_cap);
+  if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
+    delete B;
+    return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");
+  }
+  ImageLayout &L = B->lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.hdr = take(hdr.size() * 4);
+  L.eloc = take(eloc.size() * 4);
+  L.geom = take(geom.size() * 4);
+  L.inc = take(inc.size() * 2);
+  L.loff = take(loff.size() * 2);
+  L.fid = take(fid.size() * 4);
+  L.rvid = take(rvid.size() * 4);
+  L.roff = take(roff.size() * 4);
+  L.rslot = take(rslot.size() * 4);
+  L.heavy = take(heavy.size() * 4);
+  L.items = take(items.size() * 4);
+  L.iso = take(iso.size() * 4);
+  L.queue = take(16);
+  L.total = off;
+  B->image.assign(L.total, 0);
+  auto put = [&](size_t o, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(B->image.data() + o, src, bytes);
+  };
+  put(L.hdr, hdr.data(), hdr.size() * 4);
+  put(L.eloc, eloc.data(), eloc.size() * 4);
+  put(L.geom, geom.data(), geom.size() * 4);
+  put(L.inc, inc.data(), inc.size() * 2);
+  put(L.loff, loff.data(), loff.size() * 2);
+  put(L.fid, fid.data(), fid.size() * 4);
+  put(L.rvid, rvid.data(), rvid.size() * 4);
+  put(L.roff, roff.data(), roff.size() * 4);
+  put(L.rslot, rslot.data(), rslot.size() * 4);
+  put(L.heavy, heavy.data(), heavy.size() * 4);
+  put(L.items, items.data(), items.size() * 4);
+  put(L.iso, iso.data(), iso.size() * 4);
+  B->ws_bytes = align256(std::max<size_t>(size_t(foff) * 5 * 4, 4));
+  *out = B;
+  return EPK_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+
+__global__ void fill_kernel(float *p, int64_t n, float v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static std::string tune_key(const epk_graph &g, const int32_t *caps, int32_t n_caps) {
+  std::ostringstream os;
+  os << g.n_vertices << ' ' << g.n_edges << ' ' << g.geom_ncomp;
+  for (int32_t i = 0; i < n_caps; ++i) os << ' ' << caps[i];
+  return os.str();
+}
+
+// Median forward time (ms) of one graph at one capacity, run out of d_scratch.
+static int time_forward(const epk_graph &g, int32_t cap, void *d_scratch, size_t scratch_bytes, hipStream_t s,
+                        float *ms_out, int32_t *wg_out) {
+  epk_plan *p = nullptr;
+  int st = epk_plan_create(&g, cap, EPK_ORDER_EP, EPK_FLUX5, &p);
+  if (st) return st;
+  size_t img = 0, ws = 0;
+  epk_plan_device_bytes(p, &img, &ws);
+  const size_t state = align256(size_t(g.n_vertices) * 5 * 4);
+  if (img + ws + 2 * state > scratch_bytes) {
+    epk_plan_destroy(p);
+    return fail(EPK_ERANGE, "autotune scratch too small");
+  }
+  uint8_t *base = static_cast<uint8_t *>(d_scratch);
+  float *q = reinterpret_cast<float *>(base + img + ws);
+  float *r = reinterpret_cast<float *>(base + img + ws + state);
+  const int64_t nq = int64_t(g.n_vertices) * 5;
+  if (nq) hipLaunchKernelGGL(fill_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, q, nq, 1.0f);
+  st = epk_plan_upload(p, base, s);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::vector<float> t;
+  for (int it = 0; it < 8 && !st; ++it) {
+    (void)hipEventRecord(e0, s);
+    st = epk_forward(p, q, r, 0.f, nullptr, base + img, s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (it >= 2) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!st) {
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    *wg_out = p->wg;
+  }
+  epk_plan_destroy(p);
+  return st;
+}
+
+}  // namespace epk
+
+using namespace epk;
+
+extern "C" {
+
+int epk_plan_upload(epk_plan *p, void *d_image, void *stream) {
+  clear_error();
+  if (!p || !d_image) return fail(EPK_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_image) % 256) return fail(EPK_EINVAL, "d_image must be 256-byte aligned");
+  const hipError_t e = hipMemcpyAsync(d_image, p->image.data(), p->lay.total, hipMemcpyHostToDevice,
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_status(e, "image upload");
+  p->d_image = d_image;
+  return EPK_OK;
+}
+
+int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (p->kind != EPK_FLUX5) return fail(EPK_ESTATE, "epk_forward needs a FLUX5 plan");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  if (p->n > 0 && (!q || !r)) return fail(EPK_EINVAL, "q or r is NULL");
+  if (p->stats.cost > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  const DevPlan P = dev_plan(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_flux_fwd(P, p->wg, size_t(p->lds_fwd), q, r, q_new, dt, static_cast<float *>(d_ws),
+                                 p->swizzle, s);
+  if (e != hipSuccess) return hip_status(e, "forward launch");
+  e = launch_reduce(P, 5, r, static_cast<const float *>(d_ws), q, q_new, dt, s);
+  return hip_status(e, "reduce launch");
+}
+
+int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (p->kind != EPK_FLUX5) return fail(EPK_ESTATE, "epk_backward needs a FLUX5 plan");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  if (p->n > 0 && (!q || !g_r || !g_q)) return fail(EPK_EINVAL, "q, g_r or g_q is NULL");
+  if (p->stats.cost > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  const DevPlan P = dev_plan(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), q, g_r, g_q, static_cast<float *>(d_ws), p->swizzle, s);
+  if (e != hipSuccess) return hip_status(e, "adjoint launch");
+  e = launch_reduce(P, 5, g_q, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s);
+  return hip_status(e, "reduce launch");
+}
+
+int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (p->kind != EPK_SPMV) return fail(EPK_ESTATE, "epk_spmv needs an SPMV plan");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  if ((p->n_x > 0 && !x) || (p->n_out > 0 && !y)) return fail(EPK_EINVAL, "x or y is NULL");
+  if (p->R > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  const DevPlan P = dev_plan(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_spmv(P, p->wg, size_t(p->lds_fwd), x, y, static_cast<float *>(d_ws), p->swizzle, s);
+  if (e != hipSuccess) return hip_status(e, "spmv launch");
+  e = launch_reduce(P, 1, y, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s);
+  return hip_status(e, "reduce launch");
+}
+
+int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp, int32_t inverse,
+                     void *stream) {
+  clear_error();
+  if (n_rows < 0 || ncomp < 1) return fail(EPK_EINVAL, "bad sizes");
+  if (n_rows > 0 && (!src || !dst || !idx)) return fail(EPK_EINVAL, "NULL argument");
+  return hip_status(launch_permute(src, dst, idx, n_rows, ncomp, inverse, static_cast<hipStream_t>(stream)),
+                    "permute launch");
+}
+
+int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out) {
+  clear_error();
+  if (!out) return fail(EPK_EINVAL, "out is NULL");
+  *out = nullptr;
+  try {
+    return batch_build(n_graphs, plans, out);
+  } catch (const std::bad_alloc &) {
+    return fail(EPK_ENOMEM, "host allocation failed while merging the batch");
+  }
+}
+
+int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes) {
+  clear_error();
+  if (!b) return fail(EPK_EINVAL, "batch is NULL");
+  if (image_bytes) *image_bytes = b->lay.total;
+  if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+  return EPK_OK;
+}
+
+int epk_batch_upload(epk_batch *b, void *d_image, void *stream) {
+  clear_error();
+  if (!b || !d_image) return fail(EPK_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_image) % 256) return fail(EPK_EINVAL, "d_image must be 256-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_status(e, "CU count");
+  const int per_cu = std::min(persistent_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false),
+                              persistent_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true));
+  b->grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, b->k));
+  e = hipMemcpyAsync(d_image, b->image.data(), b->lay.total, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_status(e, "batch upload");
+  b->d_image = d_image;
+  return EPK_OK;
+}
+
+int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset) {
+  clear_error();
+  if (!b || !vertex_offset) return fail(EPK_EINVAL, "NULL argument");
+  std::memcpy(vertex_offset, b->voff.data(), sizeof(int64_t) * b->voff.size());
+  return EPK_OK;
+}
+
+int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info) {
+  clear_error();
+  if (!b || !info) return fail(EPK_EINVAL, "NULL argument");
+  const int64_t v[7] = {b->k, b->grid, b->lds_fwd, b->bytes_fwd, b->bytes_bwd, b->wg, b->m};
+  for (int32_t i = 0; i < n_info && i < 7; ++i) info[i] = v[i];
+  return EPK_OK;
+}
+
+int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream) {
+  clear_error();
+  if (!b) return fail(EPK_EINVAL, "batch is NULL");
+  if (!b->d_image) return fail(EPK_ESTATE, "batch not uploaded");
+  if (b->n > 0 && (!q || !r || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
+  const DevPlan P = dev_batch(b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_flux_persistent(P, int(b->wg), size_t(b->lds_fwd), q, nullptr, r, static_cast<float *>(d_ws),
+                                        false, s);
+  if (e != hipSuccess) return hip_status(e, "batch forward launch");
+  return hip_status(launch_reduce(P, 5, r, static_cast<const float *>(d_ws), q, nullptr, 0.f, s), "reduce launch");
+}
+
+int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream) {
+  clear_error();
+  if (!b) return fail(EPK_EINVAL, "batch is NULL");
+  if (!b->d_image) return fail(EPK_ESTATE, "batch not uploaded");
+  if (b->n > 0 && (!q || !g_r || !g_q || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
+  const DevPlan P = dev_batch(b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_flux_persistent(P, int(b->wg), size_t(b->lds_bwd), q, g_r, g_q, static_cast<float *>(d_ws),
+                                        true, s);
+  if (e != hipSuccess) return hip_status(e, "batch adjoint launch");
+  return hip_status(launch_reduce(P, 5, g_q, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s),
+                    "reduce launch");
+}
+
+void epk_batch_destroy(epk_batch *b) { delete b; }
+
+int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps, const char *cache_path,
+                 void *d_scratch, size_t scratch_bytes, void *stream, int32_t *chosen_cap, int32_t *chosen_wg) {
+  clear_error();
+  if (!gs || n_graphs < 1 || !caps || n_caps < 1 || !chosen_cap) return fail(EPK_EINVAL, "bad arguments");
+  if (!d_scratch) return fail(EPK_EINVAL, "d_scratch is NULL");
+  for (int32_t i = 0; i < n_caps; ++i)
+    if (caps[i] < 1) return fail(EPK_EINVAL, "capacities must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // size classes: vertex-count deciles
+  std::vector<int32_t> order(static_cast<size_t>(n_graphs));
+  for (int32_t i = 0; i < n_graphs; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return gs[a].n_vertices < gs[b].n_vertices; });
+  const int n_cls = std::min<int32_t>(10, n_graphs);
+  std::map<std::string, std::pair<int32_t, int32_t>> cache;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t bar = line.find('|');
+      if (bar == std::string::npos) continue;
+      std::istringstream rest(line.substr(bar + 1));
+      int32_t c = 0, w = 0;
+      if (rest >> c >> w) cache[line.substr(0, bar)] = {c, w};
+    }
+  }
+  bool dirty = false;
+  for (int cl = 0; cl < n_cls; ++cl) {
+    const int32_t lo = int32_t(int64_t(cl) * n_graphs / n_cls), hi = int32_t(int64_t(cl + 1) * n_graphs / n_cls);
+    if (lo >= hi) continue;
+    const epk_graph &rep = gs[order[(lo + hi) / 2]];  // median member stands for the class
+    const std::string key = tune_key(rep, caps, n_caps);
+    int32_t best_cap = caps[0], best_wg = 0;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      best_cap = it->second.first;
+      best_wg = it->second.second;
+    } else {
+      float best = 1e30f;
+      for (int32_t i = 0; i < n_caps; ++i) {
+        float ms = 0;
+        int32_t wg = 0;
+        const int st = time_forward(rep, caps[i], d_scratch, scratch_bytes, s, &ms, &wg);
+        if (st == EPK_ERANGE) continue;  // capacity not runnable here
+        if (st) return st;
+        if (ms < best) {
+          best = ms;
+          best_cap = caps[i];
+          best_wg = wg;
+        }
+      }
+      if (best >= 1e30f) return fail(EPK_ERANGE, "no capacity could be timed");
+      cache[key] = {best_cap, best_wg};
+      dirty = true;
+    }
+    for (int32_t j = lo; j < hi; ++j) {
+      chosen_cap[order[j]] = best_cap;
+      if (chosen_wg) chosen_wg[order[j]] = best_wg;
+    }
+  }
+  if (cache_path && dirty) {
+    std::ofstream outf(cache_path, std::ios::trunc);
+    for (const auto &kv : cache) outf << kv.first << '|' << kv.second.first << ' ' << kv.second.second << '\n';
+  }
+  return EPK_OK;
+}
+
+}  // extern "C"

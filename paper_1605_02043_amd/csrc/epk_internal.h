@@ -1,0 +1,119 @@
+// Internal declarations shared by the host (C++) and device (HIP) parts of libepk.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "epk.h"
+
+namespace epk {
+
+constexpr int kHdrInts = 8;          // int32 per part header
+constexpr int kMaxLdsBytes = 65536;  // per-workgroup LDS the kernels may ask for
+constexpr int kHeavySlots = 64;      // replicated vertices with more partials get a workgroup each
+constexpr int kReduceBlock = 256;
+constexpr int kHeavyBlock = 256;
+
+int fail(int status, const std::string &msg);
+void clear_error();
+
+// ------------------------------------------------------------ partitioner
+
+struct Incidence {
+  std::vector<int64_t> off;  // [n + 1]
+  std::vector<int32_t> adj;  // [2m] edge ids, ascending within each vertex
+};
+
+int validate_graph(const epk_graph *g, int32_t kind_or_minus1);
+void build_incidence(int32_t n, int64_t m, const int32_t *uv, Incidence &inc);
+// nbr[4e .. 4e+3]: predecessor/successor of e in inc[u_e] and inc[v_e], -1 if absent.
+void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr);
+void greedy_growing(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
+                    std::vector<int32_t> &task);
+void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
+void partition_stats(int32_t n, int64_t m, const int32_t *uv, int32_t cap, const std::vector<int32_t> &part,
+                     const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st);
+int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
+                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out);
+
+// ------------------------------------------------------------ device image
+
+// Offsets (bytes) of the arrays inside a plan's device image.
+struct ImageLayout {
+  size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
+  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, queue = 0, items = 0, iso = 0;
+  size_t total = 0;
+};
+
+// What a kernel needs of a plan (or of a merged batch), as device pointers.
+struct DevPlan {
+  const int32_t *hdr;
+  const uint32_t *eloc;
+  const float *geom;
+  const uint16_t *inc;
+  const uint16_t *loff;
+  const int32_t *fid;
+  const int32_t *rvid;
+  const int32_t *roff;
+  const int32_t *rslot;
+  const int32_t *heavy;
+  const int32_t *items;  // batch: part ids in processing order
+  const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
+  uint32_t *queue;       // batch: [0] ticket counter, [1] exit counter
+  int64_t m;
+  int32_t k;
+  int32_t cap;
+  int32_t geom_ncomp;
+  int32_t n;          // vertices (FLUX5) / y vertices (SPMV)
+  int32_t n_active;   // FLUX5: active vertices; SPMV: active y vertices
+  int32_t R;          // replicated (reduced) vertices
+  int32_t n_heavy;
+  int32_t max_u;      // max vertices per part (FLUX5) / max x vertices per part (SPMV)
+  int32_t max_uy;     // SPMV: max y vertices per part
+  int32_t grid;       // batch: persistent grid size
+  int32_t n_iso;      // batch: entries of iso
+};
+
+}  // namespace epk
+
+struct epk_plan {
+  int32_t n = 0, n_x = 0, kind = 0, order = 0, cap = 0, geom_ncomp = 0, ncls = 1, wg = 256, swizzle = 1;
+  int64_t m = 0, k = 0;
+  std::vector<int32_t> part, task, perm;
+  std::vector<int32_t> own_begin, own_count;  // [k * ncls]
+  std::vector<int64_t> foreign_off;           // [k * ncls + 1]
+  std::vector<int32_t> foreign_ids;           // [cost]
+  epk_stats stats{};
+  // device image, host copy
+  std::vector<uint8_t> image;
+  epk::ImageLayout lay;
+  size_t ws_bytes = 0;
+  int64_t R = 0, n_heavy = 0, n_active_out = 0, n_out = 0, max_u = 0, max_uy = 0;
+  int64_t lds_fwd = 0, lds_bwd = 0;
+  int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
+  void *d_image = nullptr;
+};
+
+struct epk_batch {
+  int32_t n_graphs = 0;
+  std::vector<int64_t> voff;  // [n_graphs + 1]
+  int64_t m = 0, k = 0, n = 0;
+  std::vector<uint8_t> image;
+  epk::ImageLayout lay;
+  size_t ws_bytes = 0;
+  int64_t R = 0, n_heavy = 0, n_iso = 0, max_u = 0, max_cap = 0, grid = 0, wg = 256;
+  int64_t lds_fwd = 0, lds_bwd = 0, bytes_fwd = 0, bytes_bwd = 0;
+  void *d_image = nullptr;
+};
+
+namespace epk {
+// LDS bytes of the FLUX5 kernels for a given part shape (must match the kernels' carve-up).
+int64_t flux_fwd_lds(int64_t max_u, int64_t cap);
+int64_t flux_bwd_lds(int64_t max_u, int64_t cap);
+int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
+epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
+DevPlan dev_plan(const epk_plan *p);
+DevPlan dev_batch(const epk_batch *b);
+}  // namespace epk

@@ -1,0 +1,25 @@
+// Launchers of the device kernels (kernels.hip); used by the device API (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "epk_internal.h"
+
+namespace epk {
+
+int grid_of_parts(int k, int swizzle);
+hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q, float *r, float *qn, float dt,
+                           float *ws, int swizzle, hipStream_t s);
+hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
+                           int swizzle, hipStream_t s);
+hipError_t launch_flux_persistent(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
+                                  float *ws, bool backward, hipStream_t s);
+hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
+                       hipStream_t s);
+hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, const float *q, float *qn, float dt,
+                         hipStream_t s);
+hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int ncomp, int inverse,
+                          hipStream_t s);
+int persistent_blocks_per_cu(int wg, size_t lds, bool backward);
+
+}  // namespace epk

@@ -1,0 +1,259 @@
+// Balanced edge partition through the clone-and-connect transform (Section 3.2).
+//
+// 1. Clone-and-connect (Definition 3): each vertex of degree d becomes d clones
+//    chained into a path of d-1 auxiliary edges, clones ordered by ascending
+//    edge id (the paper chains them "in index order").
+// 2. Original edges carry a very large weight so they are never cut; here they
+//    are contracted, so a node of the transformed graph is an edge of the input
+//    and its links are the auxiliary edges at its two clones (at most four).
+// 3. Balanced vertex partition of the contracted graph.  The paper uses METIS;
+//    this library grows parts greedily: part p takes, one node at a time, the
+//    unplaced node with the most links into p (ties: smallest id), else the one
+//    with the most links to any placed node, else the smallest unplaced id.
+//    Parts hold exactly `cap` nodes except the last (hard-capacity reading of
+//    the balance constraint of Eq. 1).
+// 4. Reconstruction (Definition 4) is the identity on contracted nodes.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <queue>
+#include <string>
+
+#include "epk_internal.h"
+
+namespace epk {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+void clear_error() { g_last_error.clear(); }
+const char *last_error() { return g_last_error.c_str(); }
+
+int validate_graph(const epk_graph *g, int32_t kind) {
+  if (!g) return fail(EPK_EINVAL, "graph is NULL");
+  if (g->n_vertices < 0) return fail(EPK_EINVAL, "n_vertices < 0");
+  if (g->n_edges < 0) return fail(EPK_EINVAL, "n_edges < 0");
+  if (g->n_edges > 0 && !g->edge_uv) return fail(EPK_EINVAL, "edge_uv is NULL");
+  if (g->n_edges >= (int64_t(1) << 31)) return fail(EPK_ERANGE, "n_edges must be < 2^31");
+  const int32_t n = g->n_vertices;
+  const bool spmv = kind == EPK_SPMV;
+  if (spmv && (g->n_x < 0 || g->n_x > n)) return fail(EPK_EINVAL, "n_x out of [0, n_vertices]");
+  for (int64_t e = 0; e < g->n_edges; ++e) {
+    const int32_t u = g->edge_uv[2 * e], v = g->edge_uv[2 * e + 1];
+    if (u < 0 || u >= n || v < 0 || v >= n)
+      return fail(EPK_EINVAL, "edge " + std::to_string(e) + " has a vertex id out of range");
+    if (u == v) return fail(EPK_EINVAL, "edge " + std::to_string(e) + " is a self-loop");
+    if (spmv && !(u < g->n_x && v >= g->n_x))
+      return fail(EPK_EINVAL, "SpMV edge " + std::to_string(e) + " must join an x vertex (first) to a y vertex");
+  }
+  if (kind == EPK_FLUX5 || kind == EPK_SPMV) {
+    if (g->n_edges > 0 && !g->edge_geom) return fail(EPK_EINVAL, "edge_geom is NULL");
+    if (kind == EPK_FLUX5 && g->geom_ncomp != 2 && g->geom_ncomp != 4)
+      return fail(EPK_EINVAL, "FLUX5 needs geom_ncomp 2 (nx, ny) or 4 (nx, ny, nz, area)");
+    if (spmv && g->geom_ncomp != 1) return fail(EPK_EINVAL, "SpMV needs geom_ncomp 1 (the weight)");
+  }
+  return EPK_OK;
+}
+
+void build_incidence(int32_t n, int64_t m, const int32_t *uv, Incidence &inc) {
+  inc.off.assign(size_t(n) + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    inc.off[uv[2 * e] + 1]++;
+    inc.off[uv[2 * e + 1] + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) inc.off[v + 1] += inc.off[v];
+  inc.adj.resize(size_t(2 * m));
+  std::vector<int64_t> cur(inc.off.begin(), inc.off.end() - 1);
+  for (int64_t e = 0; e < m; ++e) {  // ascending e keeps every list sorted
+    inc.adj[cur[uv[2 * e]]++] = int32_t(e);
+    inc.adj[cur[uv[2 * e + 1]]++] = int32_t(e);
+  }
+}
+
+void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr) {
+  nbr.assign(size_t(4 * m), -1);
+  // fill count per node; each chain link (a, b) adds b to a's list and a to b's
+  std::vector<uint8_t> cnt(size_t(m), 0);
+  const int64_t n = int64_t(inc.off.size()) - 1;
+  for (int64_t v = 0; v < n; ++v) {
+    for (int64_t t = inc.off[v]; t + 1 < inc.off[v + 1]; ++t) {
+      const int32_t a = inc.adj[t], b = inc.adj[t + 1];
+      nbr[4 * size_t(a) + cnt[a]++] = b;
+      nbr[4 * size_t(b) + cnt[b]++] = a;
+    }
+  }
+  (void)uv;
+}
+
+namespace {
+// Min-heap on (255 - value) << 32 | id: pops the largest value, smallest id first.
+using Heap = std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>>;
+inline uint64_t key(uint32_t val, int32_t e) { return (uint64_t(255u - val) << 32) | uint32_t(e); }
+
+// Pop the best valid entry of `h` (unplaced and carrying the node's current value > 0).
+inline int32_t pop_best(Heap &h, const std::vector<uint8_t> &val, const std::vector<int32_t> &part) {
+  while (!h.empty()) {
+    const uint64_t k = h.top();
+    h.pop();
+    const int32_t e = int32_t(k & 0xffffffffu);
+    const uint32_t v = 255u - uint32_t(k >> 32);
+    if (part[e] == -1 && val[e] == v && v > 0) return e;
+  }
+  return -1;
+}
+}  // namespace
+
+void greedy_growing(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
+                    std::vector<int32_t> &task) {
+  part.assign(size_t(m), -1);
+  task.clear();
+  task.reserve(size_t(m));
+  if (m == 0) return;
+  const int64_t k = (m + cap - 1) / cap;
+  std::vector<uint8_t> g(size_t(m), 0), t(size_t(m), 0);
+  std::vector<int32_t> touched;
+  Heap gh, th;
+  int64_t smallest = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    const int64_t size = std::min<int64_t>(cap, m - p * cap);
+    for (int32_t f : touched) g[f] = 0;
+    touched.clear();
+    gh = Heap();
+    for (int64_t s = 0; s < size; ++s) {
+      int32_t e = pop_best(gh, g, part);
+      if (e < 0) e = pop_best(th, t, part);
+      if (e < 0) {
+        while (part[smallest] != -1) ++smallest;
+        e = int32_t(smallest);
+      }
+      part[e] = int32_t(p);
+      task.push_back(e);
+      for (int j = 0; j < 4; ++j) {
+        const int32_t f = nbr[4 * size_t(e) + j];
+        if (f < 0 || part[f] != -1) continue;
+        if (g[f] == 0) touched.push_back(f);
+        g[f]++;
+        gh.push(key(g[f], f));
+        t[f]++;
+        th.push(key(t[f], f));
+      }
+    }
+  }
+}
+
+void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task) {
+  part.resize(size_t(m));
+  task.resize(size_t(m));
+  for (int64_t e = 0; e < m; ++e) {
+    part[e] = int32_t(e / cap);
+    task[e] = int32_t(e);
+  }
+}
+
+// Definition 2 over the partition: loads, cost, replication; aux cut of the
+// index-order transform; balance factor.
+void partition_stats(int32_t n, int64_t m, const int32_t *uv, int32_t cap, const std::vector<int32_t> &part,
+                     const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st) {
+  const int64_t k = m ? (m + cap - 1) / cap : 0;
+  std::vector<int32_t> stamp(size_t(n), -1), pv(size_t(n), 0);
+  int64_t L = 0, max_pe = 0, max_pv = 0;
+  int64_t pos = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    const int64_t size = std::min<int64_t>(cap, m - p * cap);
+    int64_t nv = 0;
+    for (int64_t s = 0; s < size; ++s, ++pos) {
+      const int32_t e = task[pos];
+      for (int side = 0; side < 2; ++side) {
+        const int32_t w = uv[2 * size_t(e) + side];
+        if (stamp[w] != int32_t(p)) {
+          stamp[w] = int32_t(p);
+          pv[w]++;
+          nv++;
+        }
+      }
+    }
+    L += nv;
+    max_pe = std::max(max_pe, size);
+    max_pv = std::max(max_pv, nv);
+  }
+  int64_t n_active = 0, R = 0, S = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    if (pv[v] >= 1) n_active++;
+    if (pv[v] >= 2) {
+      R++;
+      S += pv[v];
+    }
+  }
+  int64_t cut = 0;
+  for (int32_t v = 0; v < n; ++v)
+    for (int64_t t = inc.off[v]; t + 1 < inc.off[v + 1]; ++t)
+      if (part[inc.adj[t]] != part[inc.adj[t + 1]]) cut++;
+  st.n_parts = k;
+  st.loads = L;
+  st.cost = L - n_active;
+  st.replicated = R;
+  st.slots = S;
+  st.aux_cut = cut;
+  st.n_active = n_active;
+  st.max_part_edges = max_pe;
+  st.max_part_vertices = max_pv;
+  st.balance = (m && k) ? double(max_pe) / (double(m) / double(k)) : 0.0;
+}
+
+int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
+                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
+  if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
+  if (order != EPK_ORDER_EP && order != EPK_ORDER_INPUT) return fail(EPK_EINVAL, "unknown order");
+  std::memset(&st, 0, sizeof(st));
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    Incidence inc;
+    build_incidence(g->n_vertices, g->n_edges, g->edge_uv, inc);
+    if (order == EPK_ORDER_EP) {
+      std::vector<int32_t> nbr;
+      contracted_links(g->n_edges, g->edge_uv, inc, nbr);
+      greedy_growing(g->n_edges, cap, nbr, part, task);
+    } else {
+      input_order(g->n_edges, cap, part, task);
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    partition_stats(g->n_vertices, g->n_edges, g->edge_uv, cap, part, task, inc, st);
+    st.partition_seconds = std::chrono::duration<double>(t1 - t0).count();
+    if (inc_out) *inc_out = std::move(inc);
+  } catch (const std::bad_alloc &) {
+    return fail(EPK_ENOMEM, "host allocation failed while partitioning");
+  }
+  return EPK_OK;
+}
+
+}  // namespace epk
+
+extern "C" {
+
+int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *part_of_edge,
+                  int32_t *task_order, epk_stats *stats) {
+  epk::clear_error();
+  int s = epk::validate_graph(g, -1);
+  if (s) return s;
+  if (g->n_edges > 0 && !part_of_edge) return epk::fail(EPK_EINVAL, "part_of_edge is NULL");
+  std::vector<int32_t> part, task;
+  epk_stats st;
+  s = epk::run_partition(g, capacity, order, part, task, st, nullptr);
+  if (s) return s;
+  if (g->n_edges > 0) {
+    std::memcpy(part_of_edge, part.data(), sizeof(int32_t) * size_t(g->n_edges));
+    if (task_order) std::memcpy(task_order, task.data(), sizeof(int32_t) * size_t(g->n_edges));
+  }
+  if (stats) *stats = st;
+  return EPK_OK;
+}
+
+const char *epk_last_error(void) { return epk::last_error(); }
+const char *epk_version(void) { return "epk 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,463 @@
+// Plan: partition + data packing along the task order + the device image.
+//
+// Packing (Section 4.1, cpack): walk the tasks part by part and, inside a
+// part, in placement order; for each edge take u then v; the first touch of a
+// vertex gives it the next packed id of its class (SpMV: x and y are packed
+// apart, x into [0, n_x), y into [n_x, n)).  Untouched vertices follow in
+// ascending original id.  Hence every part OWNS a contiguous packed range
+// (the vertices it touches first) and reads its other, FOREIGN, vertices
+// from ranges owned by earlier parts.
+//
+// Per part the kernels see the local vertex list "owned range, then foreign
+// ids ascending"; a vertex's local index is its position in that list.
+// FLUX5 parts also carry a local incidence list (for each local vertex, the
+// (local edge, side) pairs in edge order) so that per-vertex sums run in a
+// fixed order.  SpMV parts keep their edges sorted by local y.
+//
+// Partials of replicated vertices: the owner writes its partial into the
+// output itself; every other part writes its partial to the workspace slot
+// (part-major, one per foreign entry; there are exactly C of them), and a
+// reduction adds the slots of each vertex in ascending part order.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "epk_internal.h"
+
+namespace epk {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t flux_fwd_lds(int64_t max_u, int64_t cap) {
+  const int64_t b = 4 * (10 * max_u + 5 * cap) + 2 * (2 * cap + max_u + 1);
+  return (b + 15) & ~int64_t(15);
+}
+int64_t flux_bwd_lds(int64_t max_u, int64_t cap) {
+  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + max_u + 1);
+  return (b + 15) & ~int64_t(15);
+}
+int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
+  const int64_t b = 4 * (max_ux + max_uy) + 8 * (wg / 64);
+  return (b + 15) & ~int64_t(15);
+}
+
+namespace {
+
+template <typename T>
+void put(std::vector<uint8_t> &img, size_t off, const std::vector<T> &v) {
+  if (!v.empty()) std::memcpy(img.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+struct Build {
+  // inputs
+  const epk_graph *g;
+  int32_t cap, kind;
+  // partition
+  std::vector<int32_t> part, task;
+  epk_stats st;
+  Incidence inc;
+  // packing
+  std::vector<int32_t> o2p, perm, first_part;
+  std::vector<int32_t> own_start;  // [(k+1) * ncls]
+};
+
+}  // namespace
+
+epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status) {
+  *status = EPK_OK;
+  if (kind != EPK_FLUX5 && kind != EPK_SPMV) {
+    *status = fail(EPK_EINVAL, "unknown kind");
+    return nullptr;
+  }
+  if ((*status = validate_graph(g, kind))) return nullptr;
+  if (cap < 1) {
+    *status = fail(EPK_EINVAL, "capacity must be >= 1");
+    return nullptr;
+  }
+  if (kind == EPK_SPMV && cap > 1024) {
+    *status = fail(EPK_ERANGE, "SpMV capacity must be <= 1024 (one edge per thread)");
+    return nullptr;
+  }
+  if (2 * int64_t(cap) > 65535) {
+    *status = fail(EPK_ERANGE, "capacity too large for 16-bit local indices");
+    return nullptr;
+  }
+  epk_plan *P = nullptr;
+  try {
+    P = new epk_plan();
+    P->n = g->n_vertices;
+    P->n_x = kind == EPK_SPMV ? g->n_x : 0;
+    P->kind = kind;
+    P->order = order;
+    P->cap = cap;
+    P->geom_ncomp = g->geom_ncomp;
+    P->ncls = kind == EPK_SPMV ? 2 : 1;
+    P->m = g->n_edges;
+    P->wg = kind == EPK_SPMV ? std::max(64, ((cap + 63) / 64) * 64) : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
+    Incidence inc;
+    int s = run_partition(g, cap, order, P->part, P->task, P->stats, &inc);
+    if (s) {
+      delete P;
+      *status = s;
+      return nullptr;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t m = P->m;
+    const int32_t n = P->n;
+    const int32_t ncls = P->ncls;
+    const int64_t k = P->stats.n_parts;
+    P->k = k;
+    const int32_t *uv = g->edge_uv;
+    auto cls = [&](int32_t w) { return (kind == EPK_SPMV && w >= P->n_x) ? 1 : 0; };
+
+    // ---- first-touch packing
+    std::vector<int32_t> o2p(size_t(n), -1), first_part(size_t(n), -1);
+    std::vector<int32_t> own_start(size_t((k + 1) * ncls), 0);
+    int32_t nxt[2] = {0, P->n_x};
+    for (int64_t p = 0, pos = 0; p < k; ++p) {
+      for (int c = 0; c < ncls; ++c) own_start[p * ncls + c] = nxt[c];
+      const int64_t ne = std::min<int64_t>(cap, m - p * cap);
+      for (int64_t j = 0; j < ne; ++j, ++pos) {
+        const int32_t e = P->task[pos];
+        for (int side = 0; side < 2; ++side) {
+          const int32_t w = uv[2 * size_t(e) + side];
+          if (o2p[w] < 0) {
+            o2p[w] = nxt[cls(w)]++;
+            first_part[w] = int32_t(p);
+          }
+        }
+      }
+    }
+    for (int c = 0; c < ncls; ++c) own_start[k * ncls + c] = nxt[c];
+    const int32_t active[2] = {nxt[0], nxt[1]};
+    for (int32_t w = 0; w < n; ++w)
+      if (o2p[w] < 0) o2p[w] = nxt[cls(w)]++;
+    P->perm.assign(size_t(n), 0);
+    for (int32_t w = 0; w < n; ++w) P->perm[o2p[w]] = w;
+
+    // ---- per-part vertex lists, local ids, kernel edge order
+    P->own_begin.assign(size_t(k * ncls), 0);
+    P->own_count.assign(size_t(k * ncls), 0);
+    P->foreign_off.assign(size_t(k * ncls + 1), 0);
+    P->foreign_ids.clear();
+    P->foreign_ids.reserve(size_t(P->stats.cost));
+    std::vector<int32_t> stamp(size_t(n), -1), loc(size_t(n), 0);
+    std::vector<uint32_t> eloc(static_cast<size_t>(m));
+    std::vector<float> geomk(size_t(m) * size_t(g->geom_ncomp));
+    std::vector<int32_t> hdr(size_t(k) * kHdrInts, 0);
+    std::vector<uint16_t> incl, loff;
+    if (kind == EPK_FLUX5) {
+      incl.resize(size_t(2 * m));
+      loff.reserve(size_t(P->stats.loads + k));
+    }
+    std::vector<int32_t> fid;  // device foreign-id list (FLUX5: all; SpMV: x only)
+    fid.reserve(size_t(P->stats.cost));
+    std::vector<int32_t> red_foreign;  // packed ids of the reduced class's foreign entries, part-major
+    int64_t max_u[2] = {0, 0};
+    std::vector<int32_t> fl[2];
+    std::vector<int32_t> cnt, cur;
+    std::vector<int64_t> order_idx;
+    int64_t lofs = 0;
+    int64_t fdev = 0;           // running x/all foreign offset in fid
+    int64_t fred = 0;           // running foreign offset of the reduced class (slot base)
+    for (int64_t p = 0, pos = 0; p < k; ++p) {
+      const int64_t e0 = p * cap;
+      const int64_t ne = std::min<int64_t>(cap, m - e0);
+      fl[0].clear();
+      fl[1].clear();
+      for (int64_t j = 0; j < ne; ++j) {
+        const int32_t e = P->task[pos + j];
+        for (int side = 0; side < 2; ++side) {
+          const int32_t w = uv[2 * size_t(e) + side];
+          if (stamp[w] == int32_t(p)) continue;
+          stamp[w] = int32_t(p);
+          if (first_part[w] != int32_t(p)) fl[cls(w)].push_back(o2p[w]);
+        }
+      }
+      int32_t own0[2], nown[2], nf[2];
+      for (int c = 0; c < ncls; ++c) {
+        own0[c] = own_start[p * ncls + c];
+        nown[c] = own_start[(p + 1) * ncls + c] - own0[c];
+        std::sort(fl[c].begin(), fl[c].end());
+        nf[c] = int32_t(fl[c].size());
+        for (int32_t i = 0; i < nf[c]; ++i) loc[P->perm[fl[c][i]]] = nown[c] + i;
+        P->own_begin[p * ncls + c] = own0[c];
+        P->own_count[p * ncls + c] = nown[c];
+        P->foreign_off[p * ncls + c + 1] = P->foreign_off[p * ncls + c] + nf[c];
+        P->foreign_ids.insert(P->foreign_ids.end(), fl[c].begin(), fl[c].end());
+        const int64_t U = int64_t(nown[c]) + nf[c];
+        if (U > 65535) {
+          delete P;
+          *status = fail(EPK_ERANGE, "a part touches more than 65535 vertices");
+          return nullptr;
+        }
+        max_u[c] = std::max(max_u[c], U);
+      }
+      auto local = [&](int32_t w) -> uint32_t {
+        const int c = cls(w);
+        return first_part[w] == int32_t(p) ? uint32_t(o2p[w] - own0[c]) : uint32_t(loc[w]);
+      };
+      int32_t *h = &hdr[size_t(p) * kHdrInts];
+      if (kind == EPK_FLUX5) {
+        const int32_t U = nown[0] + nf[0];
+        cnt.assign(size_t(U) + 1, 0);
+        for (int64_t j = 0; j < ne; ++j) {
+          const int32_t e = P->task[pos + j];
+          const uint32_t lu = local(uv[2 * size_t(e)]), lv = local(uv[2 * size_t(e) + 1]);
+          eloc[e0 + j] = lu | (lv << 16);
+          std::memcpy(&geomk[size_t(e0 + j) * g->geom_ncomp], &g->edge_geom[size_t(e) * g->geom_ncomp],
+                      sizeof(float) * g->geom_ncomp);
+          cnt[lu + 1]++;
+          cnt[lv + 1]++;
+        }
+        for (int32_t i = 0; i < U; ++i) cnt[i + 1] += cnt[i];
+        for (int32_t i = 0; i <= U; ++i) loff.push_back(uint16_t(cnt[i]));
+        cur.assign(cnt.begin(), cnt.end() - 1);
+        for (int64_t j = 0; j < ne; ++j) {  // ascending local edge: fixed summation order
+          const uint32_t w = eloc[e0 + j];
+          incl[2 * e0 + cur[w & 0xffff]++] = uint16_t((j << 1) | 0);
+          incl[2 * e0 + cur[w >> 16]++] = uint16_t((j << 1) | 1);
+        }
+        h[0] = int32_t(e0);
+        h[1] = int32_t(ne);
+        h[2] = own0[0];
+        h[3] = nown[0];
+        h[4] = int32_t(fdev);
+        h[5] = nf[0];
+        h[6] = int32_t(lofs);
+        h[7] = U;
+        lofs += U + 1;
+        fid.insert(fid.end(), fl[0].begin(), fl[0].end());
+        fdev += nf[0];
+        red_foreign.insert(red_foreign.end(), fl[0].begin(), fl[0].end());
+        fred += nf[0];
+      } else {
+        // edges of the part sorted by local y (stable in task order)
+        order_idx.resize(size_t(ne));
+        std::vector<uint32_t> ly(static_cast<size_t>(ne)), lx(static_cast<size_t>(ne));
+        for (int64_t j = 0; j < ne; ++j) {
+          const int32_t e = P->task[pos + j];
+          lx[j] = local(uv[2 * size_t(e)]);
+          ly[j] = local(uv[2 * size_t(e) + 1]);
+          order_idx[j] = j;
+        }
+        std::stable_sort(order_idx.begin(), order_idx.end(), [&](int64_t a, int64_t b) { return ly[a] < ly[b]; });
+        for (int64_t jj = 0; jj < ne; ++jj) {
+          const int64_t j = order_idx[jj];
+          const int32_t e = P->task[pos + j];
+          eloc[e0 + jj] = lx[j] | (ly[j] << 16);
+          geomk[size_t(e0 + jj)] = g->edge_geom[size_t(e)];
+        }
+        h[0] = own0[0];
+        h[1] = nown[0];
+        h[2] = int32_t(fdev);
+        h[3] = nf[0];
+        h[4] = own0[1] - P->n_x;
+        h[5] = nown[1];
+        h[6] = int32_t(fred);
+        h[7] = nf[1];
+        fid.insert(fid.end(), fl[0].begin(), fl[0].end());
+        fdev += nf[0];
+        for (int32_t v : fl[1]) red_foreign.push_back(v - P->n_x);
+        fred += nf[1];
+      }
+      pos += ne;
+    }
+    P->max_u = max_u[0];
+    P->max_uy = max_u[1];
+
+    // ---- reduction tables: for each replicated vertex of the reduced class,
+    // its slots (non-owner parts) in ascending part order.
+    const int32_t nred = kind == EPK_SPMV ? n - P->n_x : n;
+    std::vector<int32_t> scount(size_t(nred), 0);
+    for (int32_t v : red_foreign) scount[v]++;
+    std::vector<int32_t> rvid, roff(1, 0), rslot(red_foreign.size()), heavy;
+    std::vector<int32_t> start(size_t(nred), 0);
+    for (int32_t v = 0; v < nred; ++v) {
+      if (scount[v] == 0) continue;
+      start[v] = roff.back();
+      if (scount[v] > kHeavySlots) heavy.push_back(int32_t(rvid.size()));
+      rvid.push_back(v);
+      roff.push_back(roff.back() + scount[v]);
+    }
+    std::fill(scount.begin(), scount.end(), 0);
+    for (size_t s = 0; s < red_foreign.size(); ++s) {  // part-major walk: ascending part order
+      const int32_t v = red_foreign[s];
+      rslot[start[v] + scount[v]++] = int32_t(s);
+    }
+    P->R = int64_t(rvid.size());
+    P->n_heavy = int64_t(heavy.size());
+    P->n_out = nred;
+    P->n_active_out = kind == EPK_SPMV ? active[1] - P->n_x : active[0];
+
+    // ---- device image
+    ImageLayout &L = P->lay;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    L.hdr = take(hdr.size() * 4);
+    L.eloc = take(eloc.size() * 4);
+    L.geom = take(geomk.size() * 4);
+    L.inc = take(incl.size() * 2);
+    L.loff = take(loff.size() * 2);
+    L.fid = take(fid.size() * 4);
+    L.rvid = take(rvid.size() * 4);
+    L.roff = take(roff.size() * 4);
+    L.rslot = take(rslot.size() * 4);
+    L.heavy = take(heavy.size() * 4);
+    L.total = std::max<size_t>(off, 256);
+    P->image.assign(L.total, 0);
+    put(P->image, L.hdr, hdr);
+    put(P->image, L.eloc, eloc);
+    put(P->image, L.geom, geomk);
+    put(P->image, L.inc, incl);
+    put(P->image, L.loff, loff);
+    put(P->image, L.fid, fid);
+    put(P->image, L.rvid, rvid);
+    put(P->image, L.roff, roff);
+    put(P->image, L.rslot, rslot);
+    put(P->image, L.heavy, heavy);
+    const int nc = kind == EPK_SPMV ? 1 : 5;
+    P->ws_bytes = align256(std::max<size_t>(red_foreign.size() * nc * 4, 4));
+
+    // ---- LDS and algorithmic bytes
+    const int64_t C = P->stats.cost, Lds = P->stats.loads, R = P->R;
+    const int64_t Cred = int64_t(red_foreign.size());
+    if (kind == EPK_FLUX5) {
+      P->lds_fwd = flux_fwd_lds(P->max_u, cap);
+      P->lds_bwd = flux_bwd_lds(P->max_u, cap);
+      const int64_t G = g->geom_ncomp, na = P->n_active_out;
+      const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * (Lds + k) + 4 * C;
+      P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
+      P->bytes_bwd_kernel = meta + 40 * Lds + 20 * na + 20 * C;
+      P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 20 * Cred + 40 * R + 20 * (nred - na);
+      P->bytes_reduce_qnew = P->bytes_reduce + 40 * R + 40 * (nred - na);
+    } else {
+      P->lds_fwd = P->lds_bwd = spmv_lds(P->max_u, P->max_uy, P->wg);
+      // x loads = owned x + foreign x over all parts
+      int64_t Lxs = 0, Cx = 0;
+      for (int64_t p = 0; p < k; ++p) {
+        Lxs += P->own_count[p * 2] + (P->foreign_off[p * 2 + 1] - P->foreign_off[p * 2]);
+        Cx += P->foreign_off[p * 2 + 1] - P->foreign_off[p * 2];
+      }
+      const int64_t na = P->n_active_out;
+      P->bytes_fwd_kernel = 32 * k + 4 * m + 4 * m + 4 * Cx + 4 * Lxs + 4 * na + 4 * Cred;
+      P->bytes_bwd_kernel = 0;
+      P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 4 * Cred + 8 * R + 4 * (nred - na);
+      P->bytes_reduce_qnew = P->bytes_reduce;
+    }
+    if (P->lds_fwd > kMaxLdsBytes || P->lds_bwd > kMaxLdsBytes) {
+      delete P;
+      *status = fail(EPK_ERANGE, "capacity needs more LDS than a workgroup may use");
+      return nullptr;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    P->stats.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
+    return P;
+  } catch (const std::bad_alloc &) {
+    delete P;
+    *status = fail(EPK_ENOMEM, "host allocation failed while building the plan");
+    return nullptr;
+  }
+}
+
+}  // namespace epk
+
+extern "C" {
+
+int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind, epk_plan **out) {
+  epk::clear_error();
+  if (!out) return epk::fail(EPK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int s = EPK_OK;
+  epk_plan *p = epk::plan_build(g, capacity, order, kind, &s);
+  if (!p) return s ? s : epk::fail(EPK_EINVAL, "plan build failed");
+  *out = p;
+  return EPK_OK;
+}
+
+int epk_plan_device_bytes(const epk_plan *p, size_t *image_bytes, size_t *workspace_bytes) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (image_bytes) *image_bytes = p->lay.total;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  return EPK_OK;
+}
+
+int epk_plan_vertex_perm(const epk_plan *p, int32_t *packed_to_orig) {
+  epk::clear_error();
+  if (!p || (!packed_to_orig && p->n > 0)) return epk::fail(EPK_EINVAL, "NULL argument");
+  if (p->n) std::memcpy(packed_to_orig, p->perm.data(), sizeof(int32_t) * size_t(p->n));
+  return EPK_OK;
+}
+
+int epk_plan_part_of_edge(const epk_plan *p, int32_t *part_of_edge, int32_t *task_order) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (p->m) {
+    if (part_of_edge) std::memcpy(part_of_edge, p->part.data(), sizeof(int32_t) * size_t(p->m));
+    if (task_order) std::memcpy(task_order, p->task.data(), sizeof(int32_t) * size_t(p->m));
+  }
+  return EPK_OK;
+}
+
+int epk_plan_layout(const epk_plan *p, int32_t *own_begin, int32_t *own_count, int64_t *foreign_offset,
+                    int32_t *foreign_ids) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  const size_t kc = size_t(p->k) * size_t(p->ncls);
+  if (own_begin && kc) std::memcpy(own_begin, p->own_begin.data(), sizeof(int32_t) * kc);
+  if (own_count && kc) std::memcpy(own_count, p->own_count.data(), sizeof(int32_t) * kc);
+  if (foreign_offset) std::memcpy(foreign_offset, p->foreign_off.data(), sizeof(int64_t) * (kc + 1));
+  if (foreign_ids && !p->foreign_ids.empty())
+    std::memcpy(foreign_ids, p->foreign_ids.data(), sizeof(int32_t) * p->foreign_ids.size());
+  return EPK_OK;
+}
+
+int epk_plan_stats(const epk_plan *p, epk_stats *s) {
+  epk::clear_error();
+  if (!p || !s) return epk::fail(EPK_EINVAL, "NULL argument");
+  *s = p->stats;
+  return EPK_OK;
+}
+
+int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
+  epk::clear_error();
+  if (!p || !info) return epk::fail(EPK_EINVAL, "NULL argument");
+  const int64_t v[9] = {p->k,
+                        p->lds_fwd,
+                        p->lds_bwd,
+                        p->wg,
+                        p->ncls,
+                        p->bytes_fwd_kernel + p->bytes_reduce,
+                        p->bytes_bwd_kernel + p->bytes_reduce,
+                        p->bytes_fwd_kernel,
+                        p->bytes_bwd_kernel};
+  for (int32_t i = 0; i < n_info && i < 9; ++i) info[i] = v[i];
+  return EPK_OK;
+}
+
+int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (wg != 0) {
+    if (wg < 64 || wg > 1024 || wg % 64) return epk::fail(EPK_EINVAL, "workgroup must be 64..1024, multiple of 64");
+    if (p->kind == EPK_SPMV && wg < p->cap) return epk::fail(EPK_EINVAL, "SpMV workgroup must be >= capacity");
+  }
+  if (xcd_swizzle < -1 || xcd_swizzle > 1) return epk::fail(EPK_EINVAL, "xcd_swizzle must be -1, 0 or 1");
+  if (wg != 0) {
+    p->wg = wg;
+    if (p->kind == EPK_SPMV) p->lds_fwd = p->lds_bwd = epk::spmv_lds(p->max_u, p->max_uy, wg);
+  }
+  if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
+  return EPK_OK;
+}
+
+void epk_plan_destroy(epk_plan *p) { delete p; }
+
+}  // extern "C"

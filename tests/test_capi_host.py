@@ -1,0 +1,178 @@
+"""C-ABI checks that need no GPU: every declared symbol is exported, host-only
+entry points validate their inputs, and the C++ partitioner and packing agree
+bit for bit with the oracle."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import gen
+from gen.rmat import spmv_graph
+from oracle import cost, cpack, ggp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+epk = pytest.importorskip("paper_1605_02043_amd")
+from paper_1605_02043_amd import _lib  # noqa: E402
+from paper_1605_02043_amd.plan import Plan, make_graph, partition  # noqa: E402
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "epk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(epk_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 25
+    raw = C.CDLL(_lib.LIB_PATH)
+    for nm in names:
+        assert hasattr(raw, nm), nm
+    assert set(names) == set(_lib._SIGS), "binding and header disagree"
+
+
+def test_version_and_error_string():
+    assert b"epk" in _lib.lib.epk_version()
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_validation_errors():
+    lib = _lib.lib
+    part = np.zeros(4, dtype=np.int32)
+    st = _lib.Stats()
+    for edges, n, cap, code in [
+        (np.array([[0, 1], [1, 1]]), 3, 2, _lib.EPK_EINVAL),  # self-loop
+        (np.array([[0, 1], [1, 5]]), 3, 2, _lib.EPK_EINVAL),  # id out of range
+        (np.array([[0, -1]]), 3, 2, _lib.EPK_EINVAL),
+        (np.array([[0, 1]]), 3, 0, _lib.EPK_EINVAL),  # capacity < 1
+    ]:
+        gs, keep = make_graph(edges, n)
+        s = lib.epk_partition(C.byref(gs), cap, 0, _lib.i32p(part), None, C.byref(st))
+        assert s == code
+        assert len(lib.epk_last_error()) > 0
+    assert lib.epk_partition(None, 4, 0, _lib.i32p(part), None, C.byref(st)) == _lib.EPK_EINVAL
+    gs, keep = make_graph(np.array([[0, 1]]), 2)
+    assert lib.epk_partition(C.byref(gs), 4, 7, _lib.i32p(part), None, C.byref(st)) == _lib.EPK_EINVAL
+
+
+def test_plan_errors():
+    with pytest.raises(_lib.EpkError) as e:
+        Plan(np.array([[0, 1]]), 2, 4, np.zeros((1, 3), np.float32))  # bad geometry width
+    assert e.value.status == _lib.EPK_EINVAL
+    with pytest.raises(_lib.EpkError) as e:
+        Plan(np.array([[0, 1]]), 2, 4, np.ones(1, np.float32), kind="spmv", n_x=0)  # x/y classes wrong
+    assert e.value.status == _lib.EPK_EINVAL
+    with pytest.raises(_lib.EpkError) as e:
+        Plan(np.array([[0, 1]]), 2, 4096, np.zeros((1, 4), np.float32))  # LDS budget
+    assert e.value.status == _lib.EPK_ERANGE
+    with pytest.raises(_lib.EpkError) as e:
+        Plan(np.array([[0, 1]]), 2, 2048, np.ones(1, np.float32), kind="spmv", n_x=1)
+    assert e.value.status == _lib.EPK_ERANGE
+
+
+def test_device_calls_refuse_before_upload():
+    P = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
+    lib = _lib.lib
+    assert lib.epk_forward(P._h, None, None, 0.0, None, None, None) == _lib.EPK_ESTATE
+    assert lib.epk_backward(P._h, None, None, None, None, None) == _lib.EPK_ESTATE
+    assert lib.epk_spmv(P._h, None, None, None, None) == _lib.EPK_ESTATE  # wrong kind
+    with pytest.raises(_lib.EpkError):
+        P.set_launch(wg=100)
+
+
+# ------------------------------------------------------------------ parity with the oracle
+
+def _check_parity(edges, n, cap, order="ep", n_x=None):
+    part, task, st_ = partition(edges, n, cap, order)
+    p2, t2 = ggp.partition(edges, n, cap, order)
+    assert np.array_equal(part, p2) and np.array_equal(task, t2)
+    c = cost.partition_cost(edges, n, p2)
+    for key in ("n_parts", "loads", "cost", "replicated", "slots", "aux_cut", "n_active", "max_part_edges",
+                "max_part_vertices"):
+        assert st_[key] == c[key], key
+    assert st_["balance"] == pytest.approx(c["balance"], rel=1e-12)
+    return part, task, p2, t2
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(2, 60), st.integers(0, 200), st.integers(1, 40), st.integers(0, 10_000),
+       st.sampled_from(["ep", "input"]))
+def test_partition_parity_random(n, m, cap, seed, order):
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n, m)
+    v = (u + 1 + rng.integers(0, n - 1, m)) % n
+    E = np.stack([u, v], 1).astype(np.int32)
+    _check_parity(E, n, cap, order)
+
+
+def test_partition_parity_grid64_and_fig1(golden_dir):
+    G = gen.grid2d(64, 64, seed=0)
+    _check_parity(G["edges"], G["n"], 256)
+    _check_parity(G["edges"], G["n"], 256, "input")
+    import json
+
+    F = json.load(open(os.path.join(golden_dir, "fig1.json")))
+    part, _, st_ = partition(np.array(F["edges"]), F["n"], 3)
+    assert part.tolist() == F["ep_parts"] and st_["loads"] == 7
+    part, _, st_ = partition(np.array(F["edges"]), F["n"], 3, "input")
+    assert st_["loads"] == 9
+
+
+def test_partition_parity_tet_mesh():
+    T = gen.tet_mesh(16, 16, 16, seed=1)
+    for cap in (64, 256):
+        _check_parity(T["edges"], T["n"], cap)
+
+
+def test_partition_parity_rmat_bipartite():
+    R = gen.rmat(scale=12, n_edges=40_000, seed=2)
+    g = spmv_graph(R, R["shuffle"])
+    _check_parity(g["edges"], g["n"], 256)
+
+
+def _check_layout(edges, n, cap, geom, kind="flux5", n_x=0, order="ep"):
+    P = Plan(edges, n, cap, geom, order=order, kind=kind, n_x=n_x)
+    part, task = P.part_of_edge()
+    lay = cpack.layout(edges, n, part, task, n_x=n_x if kind == "spmv" else None)
+    assert np.array_equal(P.perm(), lay["perm"])
+    L = P.layout()
+    ncls = 2 if kind == "spmv" else 1
+    fo, fi = L["foreign_offset"], L["foreign_ids"]
+    for p, info in enumerate(lay["parts"]):
+        for c in range(ncls):
+            assert L["own_begin"][p, c] == info["own0"][c]
+            assert L["own_count"][p, c] == info["nown"][c]
+            s, e = fo[p * ncls + c], fo[p * ncls + c + 1]
+            assert np.array_equal(fi[s:e], info["foreign"][c])
+    stt = P.stats
+    assert stt["loads"] == sum(int(L["own_count"][p].sum()) for p in range(stt["n_parts"])) + len(fi)
+    assert stt["cost"] == len(fi)
+
+
+def test_layout_parity_flux():
+    G = gen.grid2d(30, 20, seed=3)
+    _check_layout(G["edges"], G["n"], 64, G["geom"].astype(np.float32))
+    _check_layout(G["edges"], G["n"], 64, G["geom"].astype(np.float32), order="input")
+    T = gen.tet_mesh(6, 5, 4, seed=3)
+    _check_layout(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
+
+
+def test_layout_parity_spmv_and_isolated():
+    R = gen.rmat(scale=10, n_edges=6000, seed=5)
+    g = spmv_graph(R, R["shuffle"])
+    _check_layout(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"])
+    _check_layout(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"], order="input")
+
+
+def test_plan_handles_empty_graph():
+    P = Plan(np.zeros((0, 2), np.int32), 5, 16, np.zeros((0, 4), np.float32))
+    assert P.stats["n_parts"] == 0 and P.stats["loads"] == 0
+    assert sorted(P.perm().tolist()) == list(range(5))
