@@ -1,0 +1,224 @@
+"""Benchmark: partition-ordered FLUX5 forward + adjoint on one MI355X.
+
+Workload (default): the 3D tetrahedral-mesh dual graph of a Kuhn 55^3 box,
+n = 998,250 cells, m = 1,978,350 interior faces, 5 float32 states per cell,
+face normal + area per edge, capacity 256, loss = sum r^2 (upstream gradient
+2r).  One step = forward (part kernel + reduction) then adjoint (part kernel
++ reduction) over the whole mesh, inputs resident in HBM.  The partitioned
+(EP) order gives `value`; the default (cell-major input) order is timed the
+same way alongside.
+
+Prints one JSON line.  Per-kernel durations come from HIP events recorded on
+the launch stream around every kernel of the timed steps.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tet55", choices=["tet55", "tet32"])
+    ap.add_argument("--cap", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-default-order", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def _step(P, torch, q, gr, r, gq, ev):
+    """One fwd+bwd step through the C ABI; ev: 5 events or None."""
+    from paper_1605_02043_amd._lib import check, lib
+    from paper_1605_02043_amd.plan import _dptr
+
+    s = torch.cuda.current_stream()
+    h = C_void(s.cuda_stream)
+    ws = _dptr(P.workspace)
+    calls = [(0, 0, q, None, r), (0, 1, q, None, r), (1, 0, q, gr, gq), (1, 1, q, gr, gq)]
+    for i, (op, stage, a, b, out) in enumerate(calls):
+        if ev is not None:
+            ev[i].record(s)
+        check(lib.epk_run_stage(P._h, op, stage, _dptr(a), _dptr(b), _dptr(out), 0.0, None, ws, h))
+    if ev is not None:
+        ev[4].record(s)
+
+
+def C_void(x):
+    import ctypes
+
+    return ctypes.c_void_p(x)
+
+
+def run_order(G, order, cap, steps, warmup, torch):
+    from paper_1605_02043_amd import Plan
+
+    import gen
+
+    t0 = time.perf_counter()
+    P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order).upload("cuda")
+    plan_s = time.perf_counter() - t0
+    perm = P.perm()
+    q = torch.from_numpy(gen.flux_state(G["n"], seed=0)[perm]).cuda()
+    gr = torch.from_numpy(gen.workloads.grad_seed(G["n"], seed=0)[perm]).cuda()
+    r = torch.empty_like(q)
+    gq = torch.empty_like(q)
+    for _ in range(warmup):
+        _step(P, torch, q, gr, r, gq, None)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _step(P, torch, q, gr, r, gq, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ["flux_fwd", "reduce_fwd", "flux_bwd", "reduce_bwd"]
+    dur = {nm: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, nm in enumerate(names)}
+    step_gpu = float(np.mean([e[0].elapsed_time(e[4]) for e in evs]))
+    info = P.info()
+    st = P.stats
+    m = len(G["edges"])
+    return {
+        "plan": P,
+        "wall_ms_per_step": wall / steps * 1e3,
+        "gpu_ms_per_step": step_gpu,
+        "kernel_ms": dur,
+        "info": info,
+        "stats": st,
+        "plan_seconds": plan_s,
+        "bytes_per_edge_fwd_bwd": (info["bytes_fwd"] + info["bytes_bwd"]) / m,
+        "edges_per_s": m / (wall / steps),
+    }
+
+
+def cpu_baseline(G, budget_s):
+    """The FP64 oracle (numpy, one thread) on the same workload: forward + adjoint."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import gen
+    from oracle import flux
+
+    q = gen.flux_state(G["n"], seed=0).astype(np.float64)
+    gr = gen.workloads.grad_seed(G["n"], seed=0).astype(np.float64)
+    geom = G["geom"].astype(np.float32).astype(np.float64)
+    m_all = len(G["edges"])
+    # bounded sample: a contiguous slice of the edge list sized to the budget
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        if ctx:
+            ctx.__enter__()
+        m_s = min(m_all, 200_000)
+        E = G["edges"][:m_s]
+        t0 = time.perf_counter()
+        flux.forward(G["n"], E, geom[:m_s], q)
+        flux.backward(G["n"], E, geom[:m_s], q, gr)
+        t_small = time.perf_counter() - t0
+        per_edge = t_small / m_s
+        m_s = int(min(m_all, max(m_s, budget_s / max(per_edge, 1e-12))))
+        E = G["edges"][:m_s]
+        t0 = time.perf_counter()
+        flux.forward(G["n"], E, geom[:m_s], q)
+        flux.backward(G["n"], E, geom[:m_s], q, gr)
+        t = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": m_s / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m_s} of {m_all} edges (all {G['n']} cells' states), FP64 forward + adjoint, "
+                      f"{t:.1f} s on {platform.processor() or platform.machine()} "
+                      f"(host reports {os.cpu_count()} CPUs; 1 thread used)"}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    G = gen.workload(args.workload, seed=0)
+    m = len(G["edges"])
+    print(f"# workload {args.workload}: n={G['n']} m={m}", file=sys.stderr, flush=True)
+    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch)
+    print(f"# ep: {ep['wall_ms_per_step']:.4f} ms/step kernels {ep['kernel_ms']}", file=sys.stderr, flush=True)
+    default = None
+    if not args.no_default_order:
+        default = run_order(G, "input", args.cap, args.steps, args.warmup, torch)
+        print(f"# default: {default['wall_ms_per_step']:.4f} ms/step kernels {default['kernel_ms']}", file=sys.stderr,
+              flush=True)
+    # dominant kernel of the partitioned step
+    k_ms = ep["kernel_ms"]
+    dom = max(k_ms, key=k_ms.get)
+    info = ep["info"]
+    algo = {"flux_fwd": info["bytes_fwd_kernel"], "flux_bwd": info["bytes_bwd_kernel"],
+            "reduce_fwd": info["bytes_fwd"] - info["bytes_fwd_kernel"],
+            "reduce_bwd": info["bytes_bwd"] - info["bytes_bwd_kernel"]}
+    achieved = algo[dom] / (k_ms[dom] * 1e-3) / 1e9
+    per_kernel = {nm: {"ms": k_ms[nm], "algorithmic_bytes": algo[nm],
+                       "GB/s": algo[nm] / (k_ms[nm] * 1e-3) / 1e9} for nm in k_ms}
+    st = ep["stats"]
+    out = {
+        "metric": "edges/s + DRAM bytes/edge, partitioned vs default order, fwd+bwd, 1 MI355X",
+        "value": ep["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ep["wall_ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: 3D Kuhn-tetrahedral mesh dual, n={G['n']} cells, m={m} faces, "
+                        f"5xFP32 state U[0.5,1.5], normal+area per face, capacity {args.cap}, forward + adjoint "
+                        f"(loss sum r^2), partitioned (EP) task order",
+            "capacity": args.cap,
+            "order": "ep",
+        },
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernels": per_kernel,
+        "gpu_ms_per_step": ep["gpu_ms_per_step"],
+        "algorithmic_bytes_per_edge": {"ep": ep["bytes_per_edge_fwd_bwd"]},
+        "partition": {"loads_per_edge": st["loads"] / m, "cost": st["cost"], "replicated": st["replicated"],
+                      "slots": st["slots"], "balance": st["balance"], "n_parts": st["n_parts"],
+                      "partition_seconds": st["partition_seconds"], "plan_seconds": ep["plan_seconds"]},
+    }
+    if default is not None:
+        dst = default["stats"]
+        out["default_order"] = {"value": default["edges_per_s"], "ms_per_step": default["wall_ms_per_step"],
+                                "kernels_ms": default["kernel_ms"], "loads_per_edge": dst["loads"] / m,
+                                "algorithmic_bytes_per_edge": default["bytes_per_edge_fwd_bwd"]}
+        out["algorithmic_bytes_per_edge"]["default"] = default["bytes_per_edge_fwd_bwd"]
+        out["speedup_vs_default_order"] = default["wall_ms_per_step"] / ep["wall_ms_per_step"]
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(G, args.cpu_budget_s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,19 @@ int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_
 int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream);
 /* SPMV: y[n_y] = A x[n_x] in packed x / y ids (y packed id - n_x).        */
 int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream);
+/* The two launches behind epk_forward / epk_backward / epk_spmv, for
+ * callers that time or schedule them apart.  stage 0: the part kernel
+ * (owned outputs, workspace partials); stage 1: the reduction (adds the
+ * partials of replicated vertices in ascending part order, zeroes untouched
+ * vertices, finishes q_new).  Stage 1 must follow stage 0 on the same stream
+ * with the same buffers.  kind-specific arguments as above; unused ones may
+ * be NULL (g_r for forward/spmv, dt/q_new for backward/spmv).            */
+int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
+                  float dt, float *q_new, void *d_ws, void *stream);
+/* op codes of epk_run_stage */
+#define EPK_OP_FORWARD 0
+#define EPK_OP_BACKWARD 1
+#define EPK_OP_SPMV 2
 /* dst[i] = src[idx[i]] (inverse = 0) or dst[idx[i]] = src[i] (inverse = 1),
  * rows of ncomp float32; packs states into / out of packed order.         */
 int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp,

@@ -293,50 +293,63 @@ int epk_plan_upload(epk_plan *p, void *d_image, void *stream) {
   return EPK_OK;
 }
 
-int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream) {
-  clear_error();
+static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
+                     float dt, float *q_new, void *d_ws, void *stream) {
   if (!p) return fail(EPK_EINVAL, "plan is NULL");
-  if (p->kind != EPK_FLUX5) return fail(EPK_ESTATE, "epk_forward needs a FLUX5 plan");
+  if (op < EPK_OP_FORWARD || op > EPK_OP_SPMV) return fail(EPK_EINVAL, "unknown op");
+  if (stage < -1 || stage > 1) return fail(EPK_EINVAL, "stage must be 0 or 1");
+  if ((op == EPK_OP_SPMV) != (p->kind == EPK_SPMV)) return fail(EPK_ESTATE, "op does not match the plan's kind");
   if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
-  if (p->n > 0 && (!q || !r)) return fail(EPK_EINVAL, "q or r is NULL");
-  if (p->stats.cost > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  if (op == EPK_OP_SPMV) {
+    if ((p->n_x > 0 && !in) || (p->n_out > 0 && !out)) return fail(EPK_EINVAL, "x or y is NULL");
+    if (p->R > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  } else {
+    if (p->n > 0 && (!in || !out)) return fail(EPK_EINVAL, "state or output is NULL");
+    if (op == EPK_OP_BACKWARD && p->n > 0 && !g_r) return fail(EPK_EINVAL, "g_r is NULL");
+    if (p->stats.cost > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  }
   const DevPlan P = dev_plan(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_fwd(P, p->wg, size_t(p->lds_fwd), q, r, q_new, dt, static_cast<float *>(d_ws),
-                                 p->swizzle, s);
-  if (e != hipSuccess) return hip_status(e, "forward launch");
-  e = launch_reduce(P, 5, r, static_cast<const float *>(d_ws), q, q_new, dt, s);
-  return hip_status(e, "reduce launch");
+  float *ws = static_cast<float *>(d_ws);
+  if (op == EPK_OP_BACKWARD) q_new = nullptr;
+  if (stage != 1) {  // -1 runs both
+    hipError_t e = hipSuccess;
+    if (op == EPK_OP_FORWARD)
+      e = launch_flux_fwd(P, p->wg, size_t(p->lds_fwd), in, out, q_new, dt, ws, p->swizzle, s);
+    else if (op == EPK_OP_BACKWARD)
+      e = launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), in, g_r, out, ws, p->swizzle, s);
+    else
+      e = launch_spmv(P, p->wg, size_t(p->lds_fwd), in, out, ws, p->swizzle, s);
+    if (e != hipSuccess) return hip_status(e, "part kernel launch");
+  }
+  if (stage != 0) {
+    const int nc = op == EPK_OP_SPMV ? 1 : 5;
+    const float *qin = op == EPK_OP_FORWARD ? in : nullptr;
+    return hip_status(launch_reduce(P, nc, out, ws, qin, q_new, dt, s), "reduce launch");
+  }
+  return EPK_OK;
+}
+
+int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
+                  float dt, float *q_new, void *d_ws, void *stream) {
+  clear_error();
+  if (stage != 0 && stage != 1) return fail(EPK_EINVAL, "stage must be 0 or 1");
+  return run_stage(p, op, stage, in, g_r, out, dt, q_new, d_ws, stream);
+}
+
+int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream) {
+  clear_error();
+  return run_stage(p, EPK_OP_FORWARD, -1, q, nullptr, r, dt, q_new, d_ws, stream);
 }
 
 int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream) {
   clear_error();
-  if (!p) return fail(EPK_EINVAL, "plan is NULL");
-  if (p->kind != EPK_FLUX5) return fail(EPK_ESTATE, "epk_backward needs a FLUX5 plan");
-  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
-  if (p->n > 0 && (!q || !g_r || !g_q)) return fail(EPK_EINVAL, "q, g_r or g_q is NULL");
-  if (p->stats.cost > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
-  const DevPlan P = dev_plan(p);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), q, g_r, g_q, static_cast<float *>(d_ws), p->swizzle, s);
-  if (e != hipSuccess) return hip_status(e, "adjoint launch");
-  e = launch_reduce(P, 5, g_q, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s);
-  return hip_status(e, "reduce launch");
+  return run_stage(p, EPK_OP_BACKWARD, -1, q, g_r, g_q, 0.f, nullptr, d_ws, stream);
 }
 
 int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream) {
   clear_error();
-  if (!p) return fail(EPK_EINVAL, "plan is NULL");
-  if (p->kind != EPK_SPMV) return fail(EPK_ESTATE, "epk_spmv needs an SPMV plan");
-  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
-  if ((p->n_x > 0 && !x) || (p->n_out > 0 && !y)) return fail(EPK_EINVAL, "x or y is NULL");
-  if (p->R > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
-  const DevPlan P = dev_plan(p);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_spmv(P, p->wg, size_t(p->lds_fwd), x, y, static_cast<float *>(d_ws), p->swizzle, s);
-  if (e != hipSuccess) return hip_status(e, "spmv launch");
-  e = launch_reduce(P, 1, y, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s);
-  return hip_status(e, "reduce launch");
+  return run_stage(p, EPK_OP_SPMV, -1, x, nullptr, y, 0.f, nullptr, d_ws, stream);
 }
 
 int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp, int32_t inverse,

@@ -1,0 +1,87 @@
+"""GPU parity of the SpMV kernel (y_i += w_e x_j) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import gen
+from gen.rmat import spmv_graph
+from oracle import spmv
+from tests.gpu_util import assert_close, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(g, cap, order, x):
+    from paper_1605_02043_amd import Plan
+
+    P = Plan(g["edges"], g["n"], cap, g["w"], order=order, kind="spmv", n_x=g["n_x"]).upload("cuda")
+    perm = P.perm()
+    n_x = g["n_x"]
+    xp = torch.from_numpy(np.ascontiguousarray(x[perm[:n_x]])).cuda()
+    y = P.spmv(xp)
+    torch.cuda.synchronize()
+    yp = y.cpu().numpy()
+    out = np.empty(g["n"] - n_x, dtype=np.float32)
+    out[perm[n_x:] - n_x] = yp
+    return out, P
+
+
+@pytest.mark.parametrize("order", ["ep", "input"])
+@pytest.mark.parametrize("cap", [256, 64, 1024])
+def test_spmv_rmat_small(order, cap):
+    R = gen.rmat(scale=14, n_edges=1 << 18, seed=1)
+    g = spmv_graph(R, R["shuffle"])
+    say(f"case spmv scale14 order={order} cap={cap}")
+    y, P = _run(g, cap, order, R["x"])
+    ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    assert_close(f"spmv14/{order}/{cap}", y, ref, A)
+
+
+def test_spmv_rmat_full_size_three_orders():
+    R = gen.rmat(scale=20, n_edges=1 << 24, seed=0)
+    say("case spmv rmat20 full size")
+    orders = {
+        "shuffled-ep": (R["shuffle"], "ep"),
+        "shuffled": (R["shuffle"], "input"),
+        "row-sorted": (np.argsort(R["rows"], kind="stable"), "input"),
+    }
+    ref = A = None
+    for name, (perm_e, order) in orders.items():
+        g = spmv_graph(R, perm_e)
+        if ref is None:
+            ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+            A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+        say(f"case spmv rmat20 {name}")
+        y, P = _run(g, 256, order, R["x"])
+        assert_close(f"spmv20/{name}", y, ref, A)
+        if name == "shuffled-ep":
+            st = P.stats
+            say(f"  loads/edge={st['loads'] / len(g['edges']):.3f} heavy-reduced vertices present")
+
+
+def test_spmv_hub_row_and_determinism():
+    """One row holding half of all nonzeros: a heavy vertex in the reduction."""
+    rng = np.random.default_rng(5)
+    n_x, n_y, m = 4000, 300, 60_000
+    rows = np.where(rng.random(m) < 0.5, 7, rng.integers(0, n_y, m))
+    cols = rng.integers(0, n_x, m)
+    R = {"rows": rows.astype(np.int32), "cols": cols.astype(np.int32), "w": rng.random(m, dtype=np.float32),
+         "n_x": n_x, "n_y": n_y}
+    x = rng.standard_normal(n_x).astype(np.float32)
+    g = spmv_graph(R, rng.permutation(m))
+    ref = spmv.forward(n_x, n_y, g["edges"], g["w"], x)
+    A = spmv.forward_abs(n_x, n_y, g["edges"], g["w"], x)
+    for order in ("ep", "input"):
+        say(f"case spmv hub order={order}")
+        y1, P = _run(g, 128, order, x)
+        y2, _ = _run(g, 128, order, x)
+        assert np.array_equal(y1, y2)
+        assert_close(f"spmv-hub/{order}", y1, ref, A)
