@@ -39,7 +39,20 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib, torch):
+    """A plain copy kernel of known size: reads and writes mib MiB each, 5 times."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4, "launches": 5}))
 
 
 def _step(P, torch, q, gr, r, gq, ev):
@@ -159,6 +172,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy, torch)
+        return
     G = gen.workload(args.workload, seed=0)
     m = len(G["edges"])
     print(f"# workload {args.workload}: n={G['n']} m={m}", file=sys.stderr, flush=True)

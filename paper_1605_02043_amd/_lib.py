@@ -79,7 +79,14 @@ _SIGS = {
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1605_02043_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1605_02043_amd/build.py`")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 and owns
+    # the device memory and streams handed to libepk, so torch's copy must be the
+    # one loaded before libepk.so binds its libamdhip64.so.7 dependency.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

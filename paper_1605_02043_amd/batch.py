@@ -7,7 +7,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import Graph, check, i32p, i64p, lib
-from .plan import Plan, _dptr, _stream_handle, make_graph
+from .plan import Plan, _dptr, _full_device, _stream_handle, make_graph
 
 
 class Batch:
@@ -48,7 +48,7 @@ class Batch:
     def upload(self, device="cuda"):
         import torch
 
-        dev = torch.device(device)
+        dev = _full_device(torch, device)
         img, ws = self.device_bytes()
         self.image = torch.empty(img, dtype=torch.uint8, device=dev)
         self.workspace = torch.empty(max(ws, 4), dtype=torch.uint8, device=dev)
@@ -93,7 +93,7 @@ def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", s
     out_cap = np.zeros(len(graphs), dtype=np.int32)
     out_wg = np.zeros(len(graphs), dtype=np.int32)
     check(lib.epk_autotune(arr, len(graphs), i32p(c), len(c), cache_path.encode() if cache_path else None,
-                           _dptr(scratch), scratch.numel(), _stream_handle(torch, torch.device(device)),
+                           _dptr(scratch), scratch.numel(), _stream_handle(torch, _full_device(torch, device)),
                            i32p(out_cap), i32p(out_wg)))
     del keep
     return out_cap, out_wg

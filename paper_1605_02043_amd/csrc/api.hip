@@ -120,7 +120,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     const ImageLayout &L = p->lay;
     const int64_t voff = B->voff[g];
     const int64_t C = int64_t(p->foreign_ids.size());
-    const int64_t nloff = p->stats.loads + p->k;
+    const int64_t nloff = p->n_loff;
     const int32_t *h = hptr<int32_t>(p, L.hdr);
     for (int64_t q = 0; q < p->k; ++q) {
       const int32_t *hq = h + q * kHdrInts;
@@ -171,7 +171,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   std::stable_sort(items.begin(), items.end(),
                    [&](int32_t a, int32_t b) { return hdr[size_t(a) * kHdrInts + 1] > hdr[size_t(b) * kHdrInts + 1]; });
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
-  B->lds_fwd = flux_fwd_lds(B->max_u, B->max_cap);
+  B->lds_fwd = flux_fwd_lds(B->max_u, B->max_cap, false);
   B->lds_bwd = flux_bwd_lds(B->max_u, B->max_cap);
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
@@ -315,7 +315,7 @@ static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *
   if (stage != 1) {  // -1 runs both
     hipError_t e = hipSuccess;
     if (op == EPK_OP_FORWARD)
-      e = launch_flux_fwd(P, p->wg, size_t(p->lds_fwd), in, out, q_new, dt, ws, p->swizzle, s);
+      e = launch_flux_fwd(P, p->wg, size_t(q_new ? p->lds_fwd_qn : p->lds_fwd), in, out, q_new, dt, ws, p->swizzle, s);
     else if (op == EPK_OP_BACKWARD)
       e = launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), in, g_r, out, ws, p->swizzle, s);
     else
@@ -390,8 +390,8 @@ int epk_batch_upload(epk_batch *b, void *d_image, void *stream) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_status(e, "CU count");
-  const int per_cu = std::min(persistent_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false),
-                              persistent_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true));
+  const int per_cu = std::min(persistent_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false, int(b->max_cap)),
+                              persistent_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true, int(b->max_cap)));
   b->grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, b->k));
   e = hipMemcpyAsync(d_image, b->image.data(), b->lay.total, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_status(e, "batch upload");

@@ -91,7 +91,7 @@ struct epk_plan {
   epk::ImageLayout lay;
   size_t ws_bytes = 0;
   int64_t R = 0, n_heavy = 0, n_active_out = 0, n_out = 0, max_u = 0, max_uy = 0;
-  int64_t lds_fwd = 0, lds_bwd = 0;
+  int64_t lds_fwd = 0, lds_fwd_qn = 0, lds_bwd = 0, n_loff = 0;
   int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
   void *d_image = nullptr;
 };
@@ -110,7 +110,7 @@ struct epk_batch {
 
 namespace epk {
 // LDS bytes of the FLUX5 kernels for a given part shape (must match the kernels' carve-up).
-int64_t flux_fwd_lds(int64_t max_u, int64_t cap);
+int64_t flux_fwd_lds(int64_t max_u, int64_t cap, bool qnew);
 int64_t flux_bwd_lds(int64_t max_u, int64_t cap);
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);

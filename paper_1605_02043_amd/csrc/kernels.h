@@ -20,6 +20,7 @@ hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, co
                          hipStream_t s);
 hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int ncomp, int inverse,
                           hipStream_t s);
-int persistent_blocks_per_cu(int wg, size_t lds, bool backward);
+int persistent_blocks_per_cu(int wg, size_t lds, bool backward, int cap);
+int edges_per_thread(int cap, int wg);
 
 }  // namespace epk

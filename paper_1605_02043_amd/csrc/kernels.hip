@@ -98,56 +98,119 @@ __device__ __forceinline__ void load_geom(const float *geom, int64_t e, float &n
   }
 }
 
-// Stage n5 = 5 * count floats: the contiguous owned block and the foreign rows.
-__device__ __forceinline__ void gather_rows(float *dst, const float *__restrict__ src, int own0, int nown,
-                                            const int32_t *__restrict__ fids, int nf, int tid, int nt) {
-  const float *so = src + int64_t(own0) * 5;
-  for (int d = tid; d < nown * 5; d += nt) dst[d] = so[d];
-  float *df = dst + nown * 5;
-  for (int d = tid; d < nf * 5; d += nt) {
-    const int j = d / 5;
-    const int c = d - 5 * j;
-    df[d] = src[int64_t(fids[j]) * 5 + c];
+// ------------------------------------------------------------------ staging
+
+#define EPK_LDS(p) ((__attribute__((address_space(3))) void *)(p))
+
+constexpr int kMaxFI = 16;  // foreign-state dwords prefetched per thread (covers 16 * wg / 5 vertices)
+
+// Copy src[0, n) to LDS dst[0, n) with direct-to-LDS loads: lane l of a wave
+// writes its dword at (wave base + 4 l); the base d - lane is wave-uniform
+// because the block size is a multiple of 64.
+__device__ __forceinline__ void dma_block(float *dst, const float *src, int n, int tid, int nt) {
+  const int lane = tid & 63;
+  for (int d = tid; d < n; d += nt) __builtin_amdgcn_global_load_lds(src + d, EPK_LDS(dst + (d - lane)), 4, 0, 0);
+}
+
+// Stage 5 * nf foreign state dwords: every foreign id is read first (one batch
+// of independent loads), then the states are fetched straight into LDS.
+__device__ __forceinline__ void dma_foreign(float *dst, const float *__restrict__ src, const int32_t *__restrict__ fids,
+                                            int nf, int tid, int nt) {
+  const int lane = tid & 63;
+  const int nfd = nf * 5;
+  int fr[kMaxFI];
+#pragma unroll
+  for (int k = 0; k < kMaxFI; ++k) {
+    const int d = tid + k * nt;
+    fr[k] = d < nfd ? fids[d / 5] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxFI; ++k) {
+    const int d = tid + k * nt;
+    if (d < nfd)
+      __builtin_amdgcn_global_load_lds(src + int64_t(fr[k]) * 5 + (d - 5 * (d / 5)), EPK_LDS(dst + (d - lane)), 4, 0, 0);
+  }
+  for (int d = tid + kMaxFI * nt; d < nfd; d += nt)  // parts wider than the prefetch window
+    __builtin_amdgcn_global_load_lds(src + int64_t(fids[d / 5]) * 5 + (d - 5 * (d / 5)), EPK_LDS(dst + (d - lane)), 4,
+                                     0, 0);
+}
+
+__device__ __forceinline__ void wait_staged() {
+  __builtin_amdgcn_s_waitcnt(0);  // all direct-to-LDS loads of this wave have landed
+  __syncthreads();
+}
+
+struct PartHdr {
+  int e0, ne, own0, nown, f0, nf, lofs, U;
+};
+
+__device__ __forceinline__ PartHdr load_hdr(const DevPlan &P, int part) {
+  const int4 *h = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
+  const int4 a = h[0], b = h[1];
+  return {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+// Incidence entries (2 u16 per edge, one dword) and offsets (U + 1 u16 from an
+// even index, read as whole dwords) into LDS.
+__device__ __forceinline__ void dma_incidence(uint16_t *inc, uint16_t *lo, const DevPlan &P, const PartHdr &h, int tid,
+                                              int nt) {
+  dma_block(reinterpret_cast<float *>(inc), reinterpret_cast<const float *>(P.inc) + h.e0, h.ne, tid, nt);
+  dma_block(reinterpret_cast<float *>(lo), reinterpret_cast<const float *>(P.loff) + (h.lofs >> 1), (h.U + 2) >> 1,
+            tid, nt);
+}
+
+template <int G, int EPT>
+__device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, int tid, int nt, uint32_t ew[EPT],
+                                           float4 eg[EPT]) {
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int j = tid + k * nt;
+    ew[k] = 0u;
+    eg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < h.ne) {
+      ew[k] = P.eloc[h.e0 + j];
+      load_geom<G>(P.geom, int64_t(h.e0) + j, eg[k].x, eg[k].y, eg[k].z, eg[k].w);
+    }
   }
 }
 
-__device__ __forceinline__ void stage_incidence(uint16_t *inc, uint16_t *lo, const DevPlan &P, int e0, int ne,
-                                                int lofs, int U, int tid, int nt) {
-  const uint32_t *gi = reinterpret_cast<const uint32_t *>(P.inc) + e0;  // 2 entries per edge
-  uint32_t *li = reinterpret_cast<uint32_t *>(inc);
-  for (int d = tid; d < ne; d += nt) li[d] = gi[d];
-  for (int d = tid; d <= U; d += nt) lo[d] = P.loff[lofs + d];
-}
+// ------------------------------------------------------------------ FLUX5 parts
 
-template <int G, bool QNEW>
+// LDS: st[max_u][5] | (QNEW: acc[max_u][5]) | flx[cap][5] | inc[2 cap] u16 | lo[max_u + 2] u16.
+// Without q_new the per-vertex sums overwrite st (no thread reads st then).
+template <int G, bool QNEW, int EPT>
 __device__ __forceinline__ void flux_fwd_part(const DevPlan &P, int part, const float *__restrict__ q,
                                               float *__restrict__ r, float *__restrict__ qn, float dt,
                                               float *__restrict__ ws, float *smem) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int32_t *h = P.hdr + int64_t(part) * kHdrInts;
-  const int e0 = h[0], ne = h[1], own0 = h[2], nown = h[3], f0 = h[4], nf = h[5], lofs = h[6], U = h[7];
+  const PartHdr h = load_hdr(P, part);
   float *st = smem;
-  float *acc = st + P.max_u * 5;
-  float *flx = acc + P.max_u * 5;
+  float *acc = QNEW ? st + P.max_u * 5 : st;
+  float *flx = (QNEW ? acc : st) + P.max_u * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
   uint16_t *lo = inc + 2 * P.cap;
 
-  gather_rows(st, q, own0, nown, P.fid + f0, nf, tid, nt);
-  stage_incidence(inc, lo, P, e0, ne, lofs, U, tid, nt);
-  __syncthreads();
+  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_foreign(st + h.nown * 5, q, P.fid + h.f0, h.nf, tid, nt);
+  wait_staged();
 
-  for (int j = tid; j < ne; j += nt) {
-    const uint32_t w = P.eloc[e0 + j];
-    float n1, n2, n3, a;
-    load_geom<G>(P.geom, int64_t(e0) + j, n1, n2, n3, a);
-    float F[5];
-    edge_flux(st + (w & 0xffffu) * 5, st + (w >> 16) * 5, n1, n2, n3, a, F);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) flx[j * 5 + c] = F[c];
+  for (int k = 0; k < EPT; ++k) {
+    const int j = tid + k * nt;
+    if (j < h.ne) {
+      float F[5];
+      edge_flux(st + (ew[k] & 0xffffu) * 5, st + (ew[k] >> 16) * 5, eg[k].x, eg[k].y, eg[k].z, eg[k].w, F);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) flx[j * 5 + c] = F[c];
+    }
   }
   __syncthreads();
 
-  for (int i = tid; i < U; i += nt) {
+  for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     const int t1 = lo[i + 1];
     for (int t = lo[i]; t < t1; ++t) {
@@ -166,53 +229,60 @@ __device__ __forceinline__ void flux_fwd_part(const DevPlan &P, int part, const 
   }
   __syncthreads();
 
-  float *ro = r + int64_t(own0) * 5;
-  for (int d = tid; d < nown * 5; d += nt) {
+  float *ro = r + int64_t(h.own0) * 5;
+  for (int d = tid; d < h.nown * 5; d += nt) {
     ro[d] = acc[d];
-    if constexpr (QNEW) qn[int64_t(own0) * 5 + d] = st[d] + dt * acc[d];
+    if constexpr (QNEW) qn[int64_t(h.own0) * 5 + d] = st[d] + dt * acc[d];
   }
-  float *wo = ws + int64_t(f0) * 5;
-  for (int d = tid; d < nf * 5; d += nt) wo[d] = acc[nown * 5 + d];
+  float *wo = ws + int64_t(h.f0) * 5;
+  for (int d = tid; d < h.nf * 5; d += nt) wo[d] = acc[h.nown * 5 + d];
 }
 
-template <int G>
+// LDS: st[max_u][5] | gs[max_u][5] (then the per-vertex sums) | vu[cap][5] | vv[cap][5] | inc | lo.
+template <int G, int EPT>
 __device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const float *__restrict__ q,
                                               const float *__restrict__ gr, float *__restrict__ gq,
                                               float *__restrict__ ws, float *smem) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int32_t *h = P.hdr + int64_t(part) * kHdrInts;
-  const int e0 = h[0], ne = h[1], own0 = h[2], nown = h[3], f0 = h[4], nf = h[5], lofs = h[6], U = h[7];
+  const PartHdr h = load_hdr(P, part);
   float *st = smem;
-  float *gs = st + P.max_u * 5;  // upstream gradients, then the per-vertex sums
+  float *gs = st + P.max_u * 5;
   float *vu = gs + P.max_u * 5;
   float *vv = vu + P.cap * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(vv + P.cap * 5);
   uint16_t *lo = inc + 2 * P.cap;
 
-  gather_rows(st, q, own0, nown, P.fid + f0, nf, tid, nt);
-  gather_rows(gs, gr, own0, nown, P.fid + f0, nf, tid, nt);
-  stage_incidence(inc, lo, P, e0, ne, lofs, U, tid, nt);
-  __syncthreads();
+  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_block(gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_foreign(st + h.nown * 5, q, P.fid + h.f0, h.nf, tid, nt);
+  dma_foreign(gs + h.nown * 5, gr, P.fid + h.f0, h.nf, tid, nt);
+  wait_staged();
 
-  for (int j = tid; j < ne; j += nt) {
-    const uint32_t w = P.eloc[e0 + j];
-    const int lu = w & 0xffffu, lv = w >> 16;
-    float n1, n2, n3, a;
-    load_geom<G>(P.geom, int64_t(e0) + j, n1, n2, n3, a);
-    float d[5], ju[5], jv[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) d[c] = a * (gs[lu * 5 + c] - gs[lv * 5 + c]);
-    euler_vjp(st + lu * 5, n1, n2, n3, d, ju);
-    euler_vjp(st + lv * 5, n1, n2, n3, d, jv);
+  for (int k = 0; k < EPT; ++k) {
+    const int j = tid + k * nt;
+    if (j < h.ne) {
+      const int lu = ew[k] & 0xffffu, lv = ew[k] >> 16;
+      const float a = eg[k].w;
+      float d[5], ju[5], jv[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      vu[j * 5 + c] = 0.5f * ju[c] + 0.5f * kSigma * d[c];
-      vv[j * 5 + c] = 0.5f * jv[c] - 0.5f * kSigma * d[c];
+      for (int c = 0; c < 5; ++c) d[c] = a * (gs[lu * 5 + c] - gs[lv * 5 + c]);
+      euler_vjp(st + lu * 5, eg[k].x, eg[k].y, eg[k].z, d, ju);
+      euler_vjp(st + lv * 5, eg[k].x, eg[k].y, eg[k].z, d, jv);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        vu[j * 5 + c] = 0.5f * ju[c] + 0.5f * kSigma * d[c];
+        vv[j * 5 + c] = 0.5f * jv[c] - 0.5f * kSigma * d[c];
+      }
     }
   }
   __syncthreads();
 
-  for (int i = tid; i < U; i += nt) {
+  for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     const int t1 = lo[i + 1];
     for (int t = lo[i]; t < t1; ++t) {
@@ -226,30 +296,30 @@ __device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const 
   }
   __syncthreads();
 
-  float *go = gq + int64_t(own0) * 5;
-  for (int d = tid; d < nown * 5; d += nt) go[d] = gs[d];
-  float *wo = ws + int64_t(f0) * 5;
-  for (int d = tid; d < nf * 5; d += nt) wo[d] = gs[nown * 5 + d];
+  float *go = gq + int64_t(h.own0) * 5;
+  for (int d = tid; d < h.nown * 5; d += nt) go[d] = gs[d];
+  float *wo = ws + int64_t(h.f0) * 5;
+  for (int d = tid; d < h.nf * 5; d += nt) wo[d] = gs[h.nown * 5 + d];
 }
 
-template <int G, bool QNEW>
+template <int G, bool QNEW, int EPT>
 __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
                                                         float *__restrict__ qn, float dt, float *__restrict__ ws,
                                                         int swizzle) {
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
-  flux_fwd_part<G, QNEW>(P, part, q, r, qn, dt, ws, smem);
+  flux_fwd_part<G, QNEW, EPT>(P, part, q, r, qn, dt, ws, smem);
 }
 
-template <int G>
+template <int G, int EPT>
 __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *__restrict__ q,
                                                         const float *__restrict__ gr, float *__restrict__ gq,
                                                         float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
-  flux_bwd_part<G>(P, part, q, gr, gq, ws, smem);
+  flux_bwd_part<G, EPT>(P, part, q, gr, gq, ws, smem);
 }
 
 // Persistent variant: a fixed grid takes parts from a queue (largest first).
@@ -277,21 +347,21 @@ __device__ __forceinline__ int next_item(const DevPlan &P, int *s_item) {
   return item;
 }
 
-template <int G>
-__global__ void __launch_bounds__(1024) flux_fwd_persistent(DevPlan P, const float *__restrict__ q,
+template <int EPT>
+__global__ void __launch_bounds__(256) flux_fwd_persistent(DevPlan P, const float *__restrict__ q,
                                                             float *__restrict__ r, float *__restrict__ ws) {
   extern __shared__ float smem[];
   __shared__ int s_item;
   for (;;) {
     const int part = next_item(P, &s_item);
     if (part < 0) break;
-    flux_fwd_part<G, false>(P, part, q, r, nullptr, 0.f, ws, smem);
+    flux_fwd_part<4, false, EPT>(P, part, q, r, nullptr, 0.f, ws, smem);
     __syncthreads();
   }
 }
 
-template <int G>
-__global__ void __launch_bounds__(1024) flux_bwd_persistent(DevPlan P, const float *__restrict__ q,
+template <int EPT>
+__global__ void __launch_bounds__(256) flux_bwd_persistent(DevPlan P, const float *__restrict__ q,
                                                             const float *__restrict__ gr, float *__restrict__ gq,
                                                             float *__restrict__ ws) {
   extern __shared__ float smem[];
@@ -299,40 +369,56 @@ __global__ void __launch_bounds__(1024) flux_bwd_persistent(DevPlan P, const flo
   for (;;) {
     const int part = next_item(P, &s_item);
     if (part < 0) break;
-    flux_bwd_part<G>(P, part, q, gr, gq, ws, smem);
+    flux_bwd_part<4, EPT>(P, part, q, gr, gq, ws, smem);
     __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ SpMV
 
+// LDS: xs[max_ux] | ys[max_uy] | per-wave carry keys and values.
 __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__restrict__ x, float *__restrict__ y,
                                                     float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int32_t *h = P.hdr + int64_t(part) * kHdrInts;
-  const int xo = h[0], xn = h[1], xf0 = h[2], xnf = h[3], yo = h[4], yn = h[5], yf0 = h[6], ynf = h[7];
+  const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
+  const int4 ha = h4[0], hb = h4[1];
+  const int xo = ha.x, xn = ha.y, xf0 = ha.z, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
   const int64_t e0 = int64_t(part) * P.cap;
   const int ne = int(min(int64_t(P.cap), P.m - e0));
   float *xs = smem;
   float *ys = xs + P.max_u;
   int *tkey = reinterpret_cast<int *>(ys + P.max_uy);
   float *tval = reinterpret_cast<float *>(tkey + (nt >> 6));
-
-  for (int d = tid; d < xn; d += nt) xs[d] = x[xo + d];
-  const int32_t *fids = P.fid + xf0;
-  for (int d = tid; d < xnf; d += nt) xs[xn + d] = x[fids[d]];
-  __syncthreads();
-
-  // one edge per thread, edges sorted by local y
-  const bool valid = tid < ne;
-  uint32_t w = valid ? P.eloc[e0 + tid] : 0u;
-  const int key = valid ? int(w >> 16) : 0x7fffffff;
-  float v = valid ? P.geom[e0 + tid] * xs[w & 0xffffu] : 0.0f;
   const int lane = tid & 63, wave = tid >> 6;
-  // inclusive segmented scan inside the wavefront
+
+  // owned x block straight to LDS; edge data and foreign x ids in one batch of loads
+  dma_block(xs, x + xo, xn, tid, nt);
+  const bool valid = tid < ne;
+  const uint32_t w = valid ? P.eloc[e0 + tid] : 0u;
+  const float wt = valid ? P.geom[e0 + tid] : 0.0f;
+  const uint32_t w_next = (lane == 63 && tid + 1 < ne) ? P.eloc[e0 + tid + 1] : 0u;
+  const int32_t *fids = P.fid + xf0;
+  int fr[kMaxFI];
+#pragma unroll
+  for (int k = 0; k < kMaxFI; ++k) {
+    const int d = tid + k * nt;
+    fr[k] = d < xnf ? fids[d] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxFI; ++k) {
+    const int d = tid + k * nt;
+    if (d < xnf) __builtin_amdgcn_global_load_lds(x + fr[k], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
+  }
+  for (int d = tid + kMaxFI * nt; d < xnf; d += nt)
+    __builtin_amdgcn_global_load_lds(x + fids[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
+  wait_staged();
+
+  // one edge per thread, edges sorted by local y: inclusive segmented scan per wavefront
+  const int key = valid ? int(w >> 16) : 0x7fffffff;
+  float v = valid ? wt * xs[w & 0xffffu] : 0.0f;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const float vu = __shfl_up(v, d, 64);
@@ -340,13 +426,13 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
     if (lane >= d && ku == key) v = vu + v;
   }
   int key_next = __shfl_down(key, 1, 64);
-  if (lane == 63) key_next = (tid + 1 < ne) ? int(P.eloc[e0 + tid + 1] >> 16) : 0x7ffffffe;
+  if (lane == 63) key_next = (tid + 1 < ne) ? int(w_next >> 16) : 0x7ffffffe;
   if (lane == 63) {
     tkey[wave] = (valid && key_next == key) ? key : -1;
     tval[wave] = v;
   }
   __syncthreads();
-  if (valid && key_next != key) {  // end of a segment
+  if (valid && key_next != key) {  // end of a segment: add the carries of earlier wavefronts
     float carry = 0.0f;
     bool has = false;
     for (int wp = wave - 1; wp >= 0 && tkey[wp] == key; --wp) {
@@ -363,32 +449,47 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
 
 // ------------------------------------------------------------------ reduction
 
-// Light vertices (<= kHeavySlots partials): one thread per (vertex, component),
+// Light vertices (<= kHeavySlots partials): one thread per vertex,
 // r_v = (((own + s_1) + s_2) + ...) in ascending part order.  Heavy vertices:
-// one workgroup each, strided partial sums then a fixed tree.  The tail
-// [n_active, n) of untouched vertices is zeroed here as well.
+// one workgroup each, strided partial sums then a fixed tree.  Untouched
+// vertices are zeroed here as well.
 template <int NC, bool QNEW>
 __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restrict__ r, const float *__restrict__ ws,
                                                      const float *__restrict__ q, float *__restrict__ qn, float dt,
                                                      int nb_light) {
   __shared__ float red[kHeavyBlock];
   if (int(blockIdx.x) < nb_light) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t rho = idx / NC;
-    const int c = int(idx - rho * NC);
+    const int64_t rho = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (rho < P.R) {
       const int s0 = P.roff[rho], s1 = P.roff[rho + 1];
       if (s1 - s0 > kHeavySlots) return;
-      const int64_t o = int64_t(P.rvid[rho]) * NC + c;
-      float s = r[o];
-      for (int t = s0; t < s1; ++t) s += ws[int64_t(P.rslot[t]) * NC + c];
-      r[o] = s;
-      if constexpr (QNEW) qn[o] = q[o] + dt * s;
+      const int64_t o = int64_t(P.rvid[rho]) * NC;
+      float s[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] = r[o + c];
+      for (int t = s0; t < s1; t += 4) {  // four slot ids per batch of loads
+        int sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sl[u] = t + u < s1 ? P.rslot[t + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (sl[u] >= 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s[c] += ws[int64_t(sl[u]) * NC + c];
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        r[o + c] = s[c];
+        if constexpr (QNEW) qn[o + c] = q[o + c] + dt * s[c];
+      }
     } else if (rho < int64_t(P.R) + (P.iso ? P.n_iso : P.n - P.n_active)) {
       const int64_t v = P.iso ? int64_t(P.iso[rho - P.R]) : int64_t(P.n_active) + (rho - P.R);
-      const int64_t o = v * NC + c;
-      r[o] = 0.0f;
-      if constexpr (QNEW) qn[o] = q[o];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        r[v * NC + c] = 0.0f;
+        if constexpr (QNEW) qn[v * NC + c] = q[v * NC + c];
+      }
     }
     return;
   }
@@ -428,68 +529,94 @@ __global__ void permute_rows_kernel(const float *__restrict__ src, float *__rest
 
 // ------------------------------------------------------------------ launchers
 
+int edges_per_thread(int cap, int wg) {
+  const int e = (cap + wg - 1) / wg;
+  return e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : e <= 8 ? 8 : -1;
+}
+
+#define EPK_EPT_SWITCH(ept, CALL) \
+  switch (ept) {                  \
+    case 1: {                     \
+      constexpr int E = 1;        \
+      CALL;                       \
+    } break;                      \
+    case 2: {                     \
+      constexpr int E = 2;        \
+      CALL;                       \
+    } break;                      \
+    case 4: {                     \
+      constexpr int E = 4;        \
+      CALL;                       \
+    } break;                      \
+    case 8: {                     \
+      constexpr int E = 8;        \
+      CALL;                       \
+    } break;                      \
+    default:                      \
+      return hipErrorInvalidValue; \
+  }
+
 hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q, float *r, float *qn, float dt,
                            float *ws, int swizzle, hipStream_t s) {
-  if (P.k > 0) {
-    const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
-    if (P.geom_ncomp == 4) {
-      if (qn)
-        hipLaunchKernelGGL((flux_fwd_kernel<4, true>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle);
-      else
-        hipLaunchKernelGGL((flux_fwd_kernel<4, false>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle);
+  if (P.k == 0) return hipSuccess;
+  const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
+  const int ept = edges_per_thread(P.cap, wg);
+  if (P.geom_ncomp == 4) {
+    if (qn) {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<4, true, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
+                                             swizzle))
     } else {
-      if (qn)
-        hipLaunchKernelGGL((flux_fwd_kernel<2, true>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle);
-      else
-        hipLaunchKernelGGL((flux_fwd_kernel<2, false>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle);
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<4, false, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
+                                             swizzle))
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  } else {
+    if (qn) {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<2, true, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
+                                             swizzle))
+    } else {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<2, false, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
+                                             swizzle))
+    }
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
                            int swizzle, hipStream_t s) {
-  if (P.k > 0) {
-    const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
-    if (P.geom_ncomp == 4)
-      hipLaunchKernelGGL((flux_bwd_kernel<4>), grid, block, lds, s, P, q, gr, gq, ws, swizzle);
-    else
-      hipLaunchKernelGGL((flux_bwd_kernel<2>), grid, block, lds, s, P, q, gr, gq, ws, swizzle);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (P.k == 0) return hipSuccess;
+  const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
+  const int ept = edges_per_thread(P.cap, wg);
+  if (P.geom_ncomp == 4) {
+    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<4, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
+  } else {
+    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<2, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t launch_flux_persistent(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
                                   float *ws, bool backward, hipStream_t s) {
-  if (P.k > 0) {
-    const dim3 grid(P.grid), block(wg);
-    if (backward)
-      hipLaunchKernelGGL((flux_bwd_persistent<4>), grid, block, lds, s, P, q, gr, out, ws);
-    else
-      hipLaunchKernelGGL((flux_fwd_persistent<4>), grid, block, lds, s, P, q, out, ws);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (P.k == 0) return hipSuccess;
+  const dim3 grid(P.grid), block(wg);
+  const int ept = edges_per_thread(P.cap, wg);
+  if (backward) {
+    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_persistent<E>), grid, block, lds, s, P, q, gr, out, ws))
+  } else {
+    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_persistent<E>), grid, block, lds, s, P, q, out, ws))
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
                        hipStream_t s) {
-  if (P.k > 0) {
-    hipLaunchKernelGGL(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (P.k == 0) return hipSuccess;
+  hipLaunchKernelGGL(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, const float *q, float *qn, float dt,
                          hipStream_t s) {
-  const int64_t light = (int64_t(P.R) + (P.iso ? P.n_iso : P.n - P.n_active)) * nc;
+  const int64_t light = int64_t(P.R) + (P.iso ? P.n_iso : P.n - P.n_active);
   const int nb_light = int((light + kReduceBlock - 1) / kReduceBlock);
   const int grid = nb_light + P.n_heavy;
   if (grid == 0) return hipSuccess;
@@ -514,12 +641,22 @@ hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int6
   return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int wg, size_t lds, bool backward) {
+int persistent_blocks_per_cu(int wg, size_t lds, bool backward, int cap) {
   int nb = 0;
-  const hipError_t e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &nb, reinterpret_cast<const void *>(&flux_bwd_persistent<4>), wg, lds)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &nb, reinterpret_cast<const void *>(&flux_fwd_persistent<4>), wg, lds);
+  hipError_t e = hipErrorInvalidValue;
+  const int ept = edges_per_thread(cap, wg);
+  const void *fn = nullptr;
+  if (backward)
+    fn = ept == 1 ? reinterpret_cast<const void *>(&flux_bwd_persistent<1>)
+       : ept == 2 ? reinterpret_cast<const void *>(&flux_bwd_persistent<2>)
+       : ept == 4 ? reinterpret_cast<const void *>(&flux_bwd_persistent<4>)
+                  : reinterpret_cast<const void *>(&flux_bwd_persistent<8>);
+  else
+    fn = ept == 1 ? reinterpret_cast<const void *>(&flux_fwd_persistent<1>)
+       : ept == 2 ? reinterpret_cast<const void *>(&flux_fwd_persistent<2>)
+       : ept == 4 ? reinterpret_cast<const void *>(&flux_fwd_persistent<4>)
+                  : reinterpret_cast<const void *>(&flux_fwd_persistent<8>);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, lds);
   if (e != hipSuccess || nb < 1) return 1;
   return nb;
 }

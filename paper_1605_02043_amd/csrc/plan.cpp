@@ -30,12 +30,13 @@ namespace epk {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int64_t flux_fwd_lds(int64_t max_u, int64_t cap) {
-  const int64_t b = 4 * (10 * max_u + 5 * cap) + 2 * (2 * cap + max_u + 1);
+// Must match the LDS carve-up of flux_fwd_part / flux_bwd_part.
+int64_t flux_fwd_lds(int64_t max_u, int64_t cap, bool qnew) {
+  const int64_t b = 4 * ((qnew ? 10 : 5) * max_u + 5 * cap) + 2 * (2 * cap + max_u + 2);
   return (b + 15) & ~int64_t(15);
 }
 int64_t flux_bwd_lds(int64_t max_u, int64_t cap) {
-  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + max_u + 1);
+  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + max_u + 2);
   return (b + 15) & ~int64_t(15);
 }
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
@@ -214,6 +215,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
         }
         for (int32_t i = 0; i < U; ++i) cnt[i + 1] += cnt[i];
         for (int32_t i = 0; i <= U; ++i) loff.push_back(uint16_t(cnt[i]));
+        if ((U + 1) & 1) loff.push_back(0);  // blocks start at even indices: staged as whole dwords
         cur.assign(cnt.begin(), cnt.end() - 1);
         for (int64_t j = 0; j < ne; ++j) {  // ascending local edge: fixed summation order
           const uint32_t w = eloc[e0 + j];
@@ -228,7 +230,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
         h[5] = nf[0];
         h[6] = int32_t(lofs);
         h[7] = U;
-        lofs += U + 1;
+        lofs += (U + 2) & ~1;
         fid.insert(fid.end(), fl[0].begin(), fl[0].end());
         fdev += nf[0];
         red_foreign.insert(red_foreign.end(), fl[0].begin(), fl[0].end());
@@ -317,6 +319,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     put(P->image, L.geom, geomk);
     put(P->image, L.inc, incl);
     put(P->image, L.loff, loff);
+    P->n_loff = int64_t(loff.size());
     put(P->image, L.fid, fid);
     put(P->image, L.rvid, rvid);
     put(P->image, L.roff, roff);
@@ -329,10 +332,11 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     const int64_t C = P->stats.cost, Lds = P->stats.loads, R = P->R;
     const int64_t Cred = int64_t(red_foreign.size());
     if (kind == EPK_FLUX5) {
-      P->lds_fwd = flux_fwd_lds(P->max_u, cap);
+      P->lds_fwd = flux_fwd_lds(P->max_u, cap, false);
+      P->lds_fwd_qn = flux_fwd_lds(P->max_u, cap, true);
       P->lds_bwd = flux_bwd_lds(P->max_u, cap);
       const int64_t G = g->geom_ncomp, na = P->n_active_out;
-      const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * (Lds + k) + 4 * C;
+      const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
       P->bytes_bwd_kernel = meta + 40 * Lds + 20 * na + 20 * C;
       P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 20 * Cred + 40 * R + 20 * (nred - na);
@@ -351,7 +355,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 4 * Cred + 8 * R + 4 * (nred - na);
       P->bytes_reduce_qnew = P->bytes_reduce;
     }
-    if (P->lds_fwd > kMaxLdsBytes || P->lds_bwd > kMaxLdsBytes) {
+    if (P->lds_fwd > kMaxLdsBytes || P->lds_fwd_qn > kMaxLdsBytes || P->lds_bwd > kMaxLdsBytes) {
       delete P;
       *status = fail(EPK_ERANGE, "capacity needs more LDS than a workgroup may use");
       return nullptr;
@@ -448,6 +452,7 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   if (wg != 0) {
     if (wg < 64 || wg > 1024 || wg % 64) return epk::fail(EPK_EINVAL, "workgroup must be 64..1024, multiple of 64");
     if (p->kind == EPK_SPMV && wg < p->cap) return epk::fail(EPK_EINVAL, "SpMV workgroup must be >= capacity");
+    if (p->kind == EPK_FLUX5 && p->cap > 8 * wg) return epk::fail(EPK_EINVAL, "FLUX5 needs capacity <= 8 * workgroup");
   }
   if (xcd_swizzle < -1 || xcd_swizzle > 1) return epk::fail(EPK_EINVAL, "xcd_swizzle must be -1, 0 or 1");
   if (wg != 0) {

@@ -43,6 +43,14 @@ def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep"):
     return part, task, st.as_dict()
 
 
+def _full_device(torch, device):
+    """torch.device with an explicit index ('cuda' -> 'cuda:<current>')."""
+    dev = torch.device(device)
+    if dev.type == "cuda" and dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    return dev
+
+
 def _stream_handle(torch, device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -129,7 +137,7 @@ class Plan:
     def upload(self, device="cuda"):
         import torch
 
-        dev = torch.device(device)
+        dev = _full_device(torch, device)
         img, ws = self.device_bytes()
         self.image = torch.empty(img, dtype=torch.uint8, device=dev)
         self.workspace = torch.empty(max(ws, 4), dtype=torch.uint8, device=dev)
