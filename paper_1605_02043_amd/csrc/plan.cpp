@@ -113,23 +113,36 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     const int32_t *uv = g->edge_uv;
     auto cls = [&](int32_t w) { return (kind == EPK_SPMV && w >= P->n_x) ? 1 : 0; };
 
-    // ---- first-touch packing
-    std::vector<int32_t> o2p(size_t(n), -1), first_part(size_t(n), -1);
-    std::vector<int32_t> own_start(size_t((k + 1) * ncls), 0);
-    int32_t nxt[2] = {0, P->n_x};
+    // ---- first-touch packing, per part ordered by the next part that touches
+    // the vertex (none first), then by first touch
+    std::vector<int32_t> o2p(size_t(n), -1), first_part(size_t(n), -1), second_part(size_t(n), -1);
+    std::vector<int32_t> touch;  // vertices in first-touch order (part-major)
+    touch.reserve(size_t(n));
+    std::vector<int64_t> touch_begin(size_t(k) + 1, 0);
     for (int64_t p = 0, pos = 0; p < k; ++p) {
-      for (int c = 0; c < ncls; ++c) own_start[p * ncls + c] = nxt[c];
+      touch_begin[p] = int64_t(touch.size());
       const int64_t ne = std::min<int64_t>(cap, m - p * cap);
       for (int64_t j = 0; j < ne; ++j, ++pos) {
         const int32_t e = P->task[pos];
         for (int side = 0; side < 2; ++side) {
           const int32_t w = uv[2 * size_t(e) + side];
-          if (o2p[w] < 0) {
-            o2p[w] = nxt[cls(w)]++;
+          if (first_part[w] < 0) {
             first_part[w] = int32_t(p);
+            touch.push_back(w);
+          } else if (second_part[w] < 0 && first_part[w] != int32_t(p)) {
+            second_part[w] = int32_t(p);
           }
         }
       }
+    }
+    touch_begin[k] = int64_t(touch.size());
+    std::vector<int32_t> own_start(size_t((k + 1) * ncls), 0);
+    int32_t nxt[2] = {0, P->n_x};
+    for (int64_t p = 0; p < k; ++p) {
+      for (int c = 0; c < ncls; ++c) own_start[p * ncls + c] = nxt[c];
+      auto b = touch.begin() + touch_begin[p], e = touch.begin() + touch_begin[p + 1];
+      std::stable_sort(b, e, [&](int32_t x, int32_t y) { return second_part[x] < second_part[y]; });
+      for (auto it = b; it != e; ++it) o2p[*it] = nxt[cls(*it)]++;
     }
     for (int c = 0; c < ncls; ++c) own_start[k * ncls + c] = nxt[c];
     const int32_t active[2] = {nxt[0], nxt[1]};

@@ -261,13 +261,19 @@ def test_cpack_layout(n, m, cap, seed):
     perm = lay["perm"]
     assert sorted(perm.tolist()) == list(range(n))
     assert (lay["orig_to_packed"][perm] == np.arange(n)).all()
-    # first-touch order along the task sequence
-    seen, expect = set(), []
+    # first touch along the task sequence, grouped per owning part, and inside a
+    # part ordered by the next part that touches the vertex (none first)
+    seen, order = set(), []
+    touched_by = {}
     for e in task:
         for w in E[e]:
+            touched_by.setdefault(int(w), set()).add(int(part[e]))
             if int(w) not in seen:
                 seen.add(int(w))
-                expect.append(int(w))
+                order.append(int(w))
+    owner = {w: min(ps) for w, ps in touched_by.items()}
+    nxt = {w: (sorted(ps)[1] if len(ps) > 1 else -1) for w, ps in touched_by.items()}
+    expect = sorted(order, key=lambda w: (owner[w], nxt[w], order.index(w)))
     iso = sorted(set(range(n)) - seen)
     assert perm.tolist() == expect + iso
     # owned ranges tile [0, n_active) in part order
