@@ -27,6 +27,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
+
+
+def source_sha256() -> str:
+    """Hash of the library sources: counter summaries are valid for one version only."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """Per-launch HBM bytes (FETCH_SIZE, WRITE_SIZE, scaled by the copy calibration)
+    from the committed counter summary, or None if it belongs to other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t if t.get("source_sha256") == source_sha256() else None
 
 
 def _args():
@@ -193,6 +218,7 @@ def main():
             "reduce_fwd": info["bytes_fwd"] - info["bytes_fwd_kernel"],
             "reduce_bwd": info["bytes_bwd"] - info["bytes_bwd_kernel"]}
     achieved = algo[dom] / (k_ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
     per_kernel = {nm: {"ms": k_ms[nm], "algorithmic_bytes": algo[nm],
                        "GB/s": algo[nm] / (k_ms[nm] * 1e-3) / 1e9} for nm in k_ms}
     st = ep["stats"]
@@ -217,7 +243,8 @@ def main():
             "order": "ep",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["ep"][dom]["bytes"] if traffic else None},
         "kernels": per_kernel,
         "gpu_ms_per_step": ep["gpu_ms_per_step"],
         "algorithmic_bytes_per_edge": {"ep": ep["bytes_per_edge_fwd_bwd"]},
@@ -232,6 +259,11 @@ def main():
                                 "algorithmic_bytes_per_edge": default["bytes_per_edge_fwd_bwd"]}
         out["algorithmic_bytes_per_edge"]["default"] = default["bytes_per_edge_fwd_bwd"]
         out["speedup_vs_default_order"] = default["wall_ms_per_step"] / ep["wall_ms_per_step"]
+    if traffic:
+        out["dram_bytes_per_edge"] = {o: sum(v["bytes"] * v["launches_per_step"] for v in traffic[o].values()) / m
+                                      for o in ("ep", "default")}
+        out["dram_counters"] = "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a 1 GiB copy"
+    out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(G, args.cpu_budget_s)
     print(json.dumps(out), flush=True)
 
