@@ -59,8 +59,10 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="tet55", choices=["tet55", "tet32"])
+    ap.add_argument("--workload", default="tet55", choices=["tet55", "tet32", "rmat20", "batch256"])
     ap.add_argument("--cap", type=int, default=256)
+    ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
+    ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -103,13 +105,15 @@ def C_void(x):
     return ctypes.c_void_p(x)
 
 
-def run_order(G, order, cap, steps, warmup, torch):
+def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1):
     from paper_1605_02043_amd import Plan
 
     import gen
 
     t0 = time.perf_counter()
-    P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order).upload("cuda")
+    P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order)
+    P.set_launch(wg, swizzle)
+    P.upload("cuda")
     plan_s = time.perf_counter() - t0
     perm = P.perm()
     q = torch.from_numpy(gen.flux_state(G["n"], seed=0)[perm]).cuda()
@@ -200,14 +204,18 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, torch)
         return
+    if args.workload == "rmat20":
+        return bench_spmv(args, torch)
+    if args.workload == "batch256":
+        return bench_batch(args, torch)
     G = gen.workload(args.workload, seed=0)
     m = len(G["edges"])
     print(f"# workload {args.workload}: n={G['n']} m={m}", file=sys.stderr, flush=True)
-    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch)
+    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle)
     print(f"# ep: {ep['wall_ms_per_step']:.4f} ms/step kernels {ep['kernel_ms']}", file=sys.stderr, flush=True)
     default = None
     if not args.no_default_order:
-        default = run_order(G, "input", args.cap, args.steps, args.warmup, torch)
+        default = run_order(G, "input", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle)
         print(f"# default: {default['wall_ms_per_step']:.4f} ms/step kernels {default['kernel_ms']}", file=sys.stderr,
               flush=True)
     # dominant kernel of the partitioned step
@@ -236,6 +244,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
+            "wg": ep["info"]["wg"],
+            "xcd_swizzle": args.swizzle,
             "workload": f"{args.workload}: 3D Kuhn-tetrahedral mesh dual, n={G['n']} cells, m={m} faces, "
                         f"5xFP32 state U[0.5,1.5], normal+area per face, capacity {args.cap}, forward + adjoint "
                         f"(loss sum r^2), partitioned (EP) task order",
@@ -265,6 +275,147 @@ def main():
         out["dram_counters"] = "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a 1 GiB copy"
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(G, args.cpu_budget_s)
+    print(json.dumps(out), flush=True)
+
+
+def _common(args, metric, value, ms, config):
+    return {"metric": metric, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
+
+
+def bench_spmv(args, torch):
+    """R-MAT 2^20 x 2^20, 2^24 nonzeros: SpMV in partitioned vs shuffled vs row-sorted order."""
+    import gen
+    from gen.rmat import spmv_graph
+    from paper_1605_02043_amd import Plan
+    from paper_1605_02043_amd._lib import check, lib
+    from paper_1605_02043_amd.plan import _dptr
+
+    R = gen.rmat(20, 1 << 24, seed=0)
+    m = len(R["rows"])
+    res = {}
+    for name, perm_e, order in (("ep", R["shuffle"], "ep"), ("shuffled", R["shuffle"], "input"),
+                                ("row_sorted", np.argsort(R["rows"], kind="stable"), "input")):
+        g = spmv_graph(R, perm_e)
+        t0 = time.perf_counter()
+        P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"])
+        P.set_launch(args.wg, args.swizzle)
+        P.upload("cuda")
+        plan_s = time.perf_counter() - t0
+        perm = P.perm()
+        x = torch.from_numpy(np.ascontiguousarray(R["x"][perm[:R["n_x"]]])).cuda()
+        y = torch.empty(R["n_y"], dtype=torch.float32, device="cuda")
+        s = torch.cuda.current_stream()
+        h = C_void(s.cuda_stream)
+        ws = _dptr(P.workspace)
+
+        def step(ev):
+            for i in range(2):
+                if ev is not None:
+                    ev[i].record(s)
+                check(lib.epk_run_stage(P._h, 2, i, _dptr(x), None, _dptr(y), 0.0, None, ws, h))
+            if ev is not None:
+                ev[2].record(s)
+
+        for _ in range(args.warmup):
+            step(None)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        kms = {"spmv": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+               "reduce": float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))}
+        info = P.info()
+        st = P.stats
+        res[name] = {"edges_per_s": m / wall, "ms_per_step": wall * 1e3, "kernels_ms": kms,
+                     "algorithmic_bytes": {"spmv": info["bytes_fwd_kernel"],
+                                           "reduce": info["bytes_fwd"] - info["bytes_fwd_kernel"]},
+                     "loads_per_edge": st["loads"] / m, "slots_per_edge": st["slots"] / m,
+                     "plan_seconds": plan_s, "partition_seconds": st["partition_seconds"]}
+        print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+        del P
+    ep = res["ep"]
+    dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
+    ach = ep["algorithmic_bytes"][dom] / (ep["kernels_ms"][dom] * 1e-3) / 1e9
+    out = _common(args, "edges/s, SpMV y += A x, partitioned vs shuffled order, 1 MI355X", ep["edges_per_s"],
+                  ep["ms_per_step"], {"workload": f"rmat20: R-MAT 2^20 x 2^20, {m} nonzeros (a,b,c)=(0.57,0.19,0.19), "
+                                                  f"w~U[0,1), x~N(0,1), capacity {args.cap}, partitioned order",
+                                      "capacity": args.cap})
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    out["orders"] = res
+    out["source_sha256"] = source_sha256()
+    out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, torch):
+    """256 uneven mesh graphs, one persistent launch each way, the fwd+bwd step replayed from a HIP graph."""
+    import gen
+    from paper_1605_02043_amd import Plan
+    from paper_1605_02043_amd.batch import Batch, autotune
+
+    t0 = time.perf_counter()
+    graphs = gen.batch_graphs(256, seed=0)
+    gen_s = time.perf_counter() - t0
+    m = sum(len(g["edges"]) for g in graphs)
+    n = sum(g["n"] for g in graphs)
+    t0 = time.perf_counter()
+    caps, wgs = autotune(graphs, caps=(64, 128, 256, 512))
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plans = [Plan(g["edges"], g["n"], int(c), g["geom"].astype(np.float32)) for g, c in zip(graphs, caps)]
+    B = Batch(plans).upload("cuda")
+    plan_s = time.perf_counter() - t0
+    q = torch.from_numpy(np.concatenate([gen.flux_state(g["n"], seed=i)[p.perm()] for i, (g, p) in
+                                         enumerate(zip(graphs, plans))])).cuda()
+    gr = torch.from_numpy(np.concatenate([gen.workloads.grad_seed(g["n"], seed=i)[p.perm()] for i, (g, p) in
+                                          enumerate(zip(graphs, plans))])).cuda()
+    r = torch.empty_like(q)
+    gq = torch.empty_like(q)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            B.forward(q, out=r)
+            B.backward(q, gr, out=gq)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.forward(q, out=r)
+        B.backward(q, gr, out=gq)
+    for _ in range(args.warmup):
+        graph.replay()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record()
+        graph.replay()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    gpu_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    info = B.info()
+    algo = info["bytes_fwd"] + info["bytes_bwd"]
+    ach = algo / (gpu_ms * 1e-3) / 1e9
+    out = _common(args, "edges/s, batched persistent FLUX5 fwd+bwd over 256 uneven meshes, HIP-graph replay, 1 MI355X",
+                  m / wall, wall * 1e3,
+                  {"workload": f"batch256: 256 2D/3D mesh graphs, vertex counts log-uniform in [1024, 65536], "
+                               f"total n={n}, m={m}, capacities autotuned per size decile", "graphs": 256})
+    out["roofline"] = {"bound": "hbm", "kernel": "graph replay (persistent fwd + reduce + persistent bwd + reduce)",
+                       "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                       "traffic": None}
+    out["batch"] = {"items": info["items"], "grid": info["grid"], "wg": info["wg"], "lds_fwd": info["lds_fwd"],
+                    "caps": {int(c): int((caps == c).sum()) for c in np.unique(caps)}, "gpu_ms_per_step": gpu_ms,
+                    "algorithmic_bytes_per_step": algo, "gen_s": gen_s, "autotune_s": tune_s, "plan_s": plan_s}
+    out["source_sha256"] = source_sha256()
+    out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 
