@@ -51,8 +51,16 @@ typedef enum {
 } epk_status;
 
 typedef enum {
-  EPK_ORDER_EP = 0,   /* edge partition through the transformed graph (Section 3.2) */
-  EPK_ORDER_INPUT = 1 /* default schedule: consecutive tasks per block, part = e / cap (Section 1) */
+  /* edge partition through the transformed graph (Section 3.2): multilevel
+   * vertex partition of the contracted clone-and-connect graph; at most cap
+   * edges per part, k = ceil(m / (cap - cap/20)) parts (some may be empty),
+   * tasks in ascending edge id inside a part */
+  EPK_ORDER_EP = 0,
+  /* default schedule: consecutive tasks per block, part = e / cap (Section 1) */
+  EPK_ORDER_INPUT = 1,
+  /* single-pass greedy growing on the same transform: k = ceil(m / cap),
+   * parts 0..k-2 hold exactly cap edges, tasks in placement order */
+  EPK_ORDER_GGP = 2
 } epk_order;
 
 typedef enum {
@@ -91,9 +99,10 @@ typedef struct epk_batch epk_batch;
 /* ------------------------------------------------------------------ host */
 
 /* The paper's problem (Eq. 1): graph + capacity in, edge -> part and cost out.
- * k = ceil(m / capacity); parts 0..k-2 hold exactly `capacity` edges.
- * part_of_edge[m] and task_order[m] are caller-allocated (task_order may be
- * NULL): task_order lists the edges part by part, in placement order.
+ * Every part holds at most `capacity` edges; k and the order inside a part
+ * depend on the order (see epk_order).  part_of_edge[m] and task_order[m]
+ * are caller-allocated (task_order may be NULL): task_order lists the edges
+ * part by part (parts ascending).
  * Host only, synchronous; geometry is not read.                          */
 int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *part_of_edge,
                   int32_t *task_order, epk_stats *stats);

@@ -29,4 +29,15 @@ those pins is parity unpinned: it is fixed by their specification and checked
 only by two independent implementations agreeing bit for bit.
 """
 
-from . import graph, cost, ggp, cpack, flux, spmv, brute  # noqa: F401
+from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute  # noqa: F401
+
+
+def partition(edges, n, cap, order="ep"):
+    """(part, task_order) for an order: 'ep' (multilevel, the default), 'ggp'
+    (single-pass greedy growing) or 'input' (consecutive blocks)."""
+    if order == "ep":
+        part, task, _ = multilevel.partition(edges, n, cap)
+        return part, task
+    if order == "ggp":
+        return ggp.partition(edges, n, cap, order="ep")
+    return ggp.partition(edges, n, cap, order="input")

@@ -27,6 +27,7 @@ DevPlan dev_plan(const epk_plan *p) {
   void *b = p->d_image;
   const ImageLayout &L = p->lay;
   P.hdr = dptr<int32_t>(b, L.hdr);
+  P.eoff = dptr<int32_t>(b, L.eoff);
   P.eloc = dptr<uint32_t>(b, L.eloc);
   P.geom = dptr<float>(b, L.geom);
   P.inc = dptr<uint16_t>(b, L.inc);
@@ -59,6 +60,7 @@ DevPlan dev_batch(const epk_batch *bt) {
   void *b = bt->d_image;
   const ImageLayout &L = bt->lay;
   P.hdr = dptr<int32_t>(b, L.hdr);
+  P.eoff = dptr<int32_t>(b, L.eoff);
   P.eloc = dptr<uint32_t>(b, L.eloc);
   P.geom = dptr<float>(b, L.geom);
   P.inc = dptr<uint16_t>(b, L.inc);

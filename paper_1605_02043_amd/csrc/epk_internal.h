@@ -33,7 +33,10 @@ void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::v
 void greedy_growing(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
                     std::vector<int32_t> &task);
 void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
-void partition_stats(int32_t n, int64_t m, const int32_t *uv, int32_t cap, const std::vector<int32_t> &part,
+int64_t multilevel_parts(int64_t m, int32_t cap);
+void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
+                std::vector<int32_t> &task);
+void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const std::vector<int32_t> &part,
                      const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st);
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out);
@@ -43,7 +46,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
-  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, queue = 0, items = 0, iso = 0;
+  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, queue = 0, items = 0, iso = 0, eoff = 0;
   size_t total = 0;
 };
 
@@ -61,6 +64,7 @@ struct DevPlan {
   const int32_t *heavy;
   const int32_t *items;  // batch: part ids in processing order
   const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
+  const int32_t *eoff;   // [k + 1] first task of every part
   uint32_t *queue;       // batch: [0] ticket counter, [1] exit counter
   int64_t m;
   int32_t k;

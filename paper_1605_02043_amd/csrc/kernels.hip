@@ -386,8 +386,8 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
   const int4 ha = h4[0], hb = h4[1];
   const int xo = ha.x, xn = ha.y, xf0 = ha.z, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
-  const int64_t e0 = int64_t(part) * P.cap;
-  const int ne = int(min(int64_t(P.cap), P.m - e0));
+  const int64_t e0 = P.eoff[part];
+  const int ne = int(P.eoff[part + 1] - e0);
   float *xs = smem;
   float *ys = xs + P.max_u;
   int *tkey = reinterpret_cast<int *>(ys + P.max_uy);

@@ -157,29 +157,29 @@ void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector
 
 // Definition 2 over the partition: loads, cost, replication; aux cut of the
 // index-order transform; balance factor.
-void partition_stats(int32_t n, int64_t m, const int32_t *uv, int32_t cap, const std::vector<int32_t> &part,
+void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const std::vector<int32_t> &part,
                      const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st) {
-  const int64_t k = m ? (m + cap - 1) / cap : 0;
   std::vector<int32_t> stamp(size_t(n), -1), pv(size_t(n), 0);
-  int64_t L = 0, max_pe = 0, max_pv = 0;
-  int64_t pos = 0;
-  for (int64_t p = 0; p < k; ++p) {
-    const int64_t size = std::min<int64_t>(cap, m - p * cap);
-    int64_t nv = 0;
-    for (int64_t s = 0; s < size; ++s, ++pos) {
-      const int32_t e = task[pos];
-      for (int side = 0; side < 2; ++side) {
-        const int32_t w = uv[2 * size_t(e) + side];
-        if (stamp[w] != int32_t(p)) {
-          stamp[w] = int32_t(p);
-          pv[w]++;
-          nv++;
-        }
+  std::vector<int64_t> size(size_t(k), 0), nverts(size_t(k), 0);
+  int64_t L = 0;
+  for (int64_t pos = 0; pos < m; ++pos) {  // task order is part-major
+    const int32_t e = task[pos];
+    const int32_t p = part[e];
+    size[p]++;
+    for (int side = 0; side < 2; ++side) {
+      const int32_t w = uv[2 * size_t(e) + side];
+      if (stamp[w] != p) {
+        stamp[w] = p;
+        pv[w]++;
+        nverts[p]++;
+        L++;
       }
     }
-    L += nv;
-    max_pe = std::max(max_pe, size);
-    max_pv = std::max(max_pv, nv);
+  }
+  int64_t max_pe = 0, max_pv = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    max_pe = std::max(max_pe, size[p]);
+    max_pv = std::max(max_pv, nverts[p]);
   }
   int64_t n_active = 0, R = 0, S = 0;
   for (int32_t v = 0; v < n; ++v) {
@@ -208,21 +208,29 @@ void partition_stats(int32_t n, int64_t m, const int32_t *uv, int32_t cap, const
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
   if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
-  if (order != EPK_ORDER_EP && order != EPK_ORDER_INPUT) return fail(EPK_EINVAL, "unknown order");
+  if (order != EPK_ORDER_EP && order != EPK_ORDER_INPUT && order != EPK_ORDER_GGP)
+    return fail(EPK_EINVAL, "unknown order");
   std::memset(&st, 0, sizeof(st));
   try {
     const auto t0 = std::chrono::steady_clock::now();
     Incidence inc;
     build_incidence(g->n_vertices, g->n_edges, g->edge_uv, inc);
-    if (order == EPK_ORDER_EP) {
-      std::vector<int32_t> nbr;
-      contracted_links(g->n_edges, g->edge_uv, inc, nbr);
-      greedy_growing(g->n_edges, cap, nbr, part, task);
+    const int64_t m = g->n_edges;
+    int64_t k = m ? (m + cap - 1) / cap : 0;
+    if (order == EPK_ORDER_INPUT) {
+      input_order(m, cap, part, task);
     } else {
-      input_order(g->n_edges, cap, part, task);
+      std::vector<int32_t> nbr;
+      contracted_links(m, g->edge_uv, inc, nbr);
+      if (order == EPK_ORDER_GGP) {
+        greedy_growing(m, cap, nbr, part, task);
+      } else {
+        k = multilevel_parts(m, cap);
+        multilevel(m, cap, nbr, part, task);
+      }
     }
     const auto t1 = std::chrono::steady_clock::now();
-    partition_stats(g->n_vertices, g->n_edges, g->edge_uv, cap, part, task, inc, st);
+    partition_stats(g->n_vertices, m, g->edge_uv, k, part, task, inc, st);
     st.partition_seconds = std::chrono::duration<double>(t1 - t0).count();
     if (inc_out) *inc_out = std::move(inc);
   } catch (const std::bad_alloc &) {

@@ -111,6 +111,10 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     const int64_t k = P->stats.n_parts;
     P->k = k;
     const int32_t *uv = g->edge_uv;
+    // parts are contiguous in the task order; poff[p] is part p's first task
+    std::vector<int64_t> poff(size_t(k) + 1, 0);
+    for (int64_t e = 0; e < m; ++e) poff[P->part[e] + 1]++;
+    for (int64_t q = 0; q < k; ++q) poff[q + 1] += poff[q];
     auto cls = [&](int32_t w) { return (kind == EPK_SPMV && w >= P->n_x) ? 1 : 0; };
 
     // ---- first-touch packing, per part ordered by the next part that touches
@@ -121,7 +125,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::vector<int64_t> touch_begin(size_t(k) + 1, 0);
     for (int64_t p = 0, pos = 0; p < k; ++p) {
       touch_begin[p] = int64_t(touch.size());
-      const int64_t ne = std::min<int64_t>(cap, m - p * cap);
+      const int64_t ne = poff[p + 1] - poff[p];
       for (int64_t j = 0; j < ne; ++j, ++pos) {
         const int32_t e = P->task[pos];
         for (int side = 0; side < 2; ++side) {
@@ -177,8 +181,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     int64_t fdev = 0;           // running x/all foreign offset in fid
     int64_t fred = 0;           // running foreign offset of the reduced class (slot base)
     for (int64_t p = 0, pos = 0; p < k; ++p) {
-      const int64_t e0 = p * cap;
-      const int64_t ne = std::min<int64_t>(cap, m - e0);
+      const int64_t e0 = poff[p];
+      const int64_t ne = poff[p + 1] - e0;
       fl[0].clear();
       fl[1].clear();
       for (int64_t j = 0; j < ne; ++j) {
@@ -315,6 +319,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       off = align256(off + bytes);
       return o;
     };
+    std::vector<int32_t> eoff(poff.begin(), poff.end());
+    L.eoff = take(eoff.size() * 4);
     L.hdr = take(hdr.size() * 4);
     L.eloc = take(eloc.size() * 4);
     L.geom = take(geomk.size() * 4);
@@ -327,6 +333,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.heavy = take(heavy.size() * 4);
     L.total = std::max<size_t>(off, 256);
     P->image.assign(L.total, 0);
+    put(P->image, L.eoff, eoff);
     put(P->image, L.hdr, hdr);
     put(P->image, L.eloc, eloc);
     put(P->image, L.geom, geomk);

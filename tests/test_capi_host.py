@@ -12,6 +12,7 @@ from hypothesis import given, settings, strategies as st
 
 import gen
 from gen.rmat import spmv_graph
+import oracle
 from oracle import cost, cpack, ggp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -92,9 +93,9 @@ def test_device_calls_refuse_before_upload():
 
 def _check_parity(edges, n, cap, order="ep", n_x=None):
     part, task, st_ = partition(edges, n, cap, order)
-    p2, t2 = ggp.partition(edges, n, cap, order)
+    p2, t2 = oracle.partition(edges, n, cap, order)
     assert np.array_equal(part, p2) and np.array_equal(task, t2)
-    c = cost.partition_cost(edges, n, p2)
+    c = cost.partition_cost(edges, n, p2, st_["n_parts"])
     for key in ("n_parts", "loads", "cost", "replicated", "slots", "aux_cut", "n_active", "max_part_edges",
                 "max_part_vertices"):
         assert st_[key] == c[key], key
@@ -104,7 +105,7 @@ def _check_parity(edges, n, cap, order="ep", n_x=None):
 
 @settings(max_examples=60, deadline=None)
 @given(st.integers(2, 60), st.integers(0, 200), st.integers(1, 40), st.integers(0, 10_000),
-       st.sampled_from(["ep", "input"]))
+       st.sampled_from(["ep", "ggp", "input"]))
 def test_partition_parity_random(n, m, cap, seed, order):
     rng = np.random.default_rng(seed)
     u = rng.integers(0, n, m)
@@ -115,8 +116,8 @@ def test_partition_parity_random(n, m, cap, seed, order):
 
 def test_partition_parity_grid64_and_fig1(golden_dir):
     G = gen.grid2d(64, 64, seed=0)
-    _check_parity(G["edges"], G["n"], 256)
-    _check_parity(G["edges"], G["n"], 256, "input")
+    for order in ("ep", "ggp", "input"):
+        _check_parity(G["edges"], G["n"], 256, order)
     import json
 
     F = json.load(open(os.path.join(golden_dir, "fig1.json")))
@@ -130,6 +131,7 @@ def test_partition_parity_tet_mesh():
     T = gen.tet_mesh(16, 16, 16, seed=1)
     for cap in (64, 256):
         _check_parity(T["edges"], T["n"], cap)
+    _check_parity(T["edges"], T["n"], 256, "ggp")
 
 
 def test_partition_parity_rmat_bipartite():
@@ -161,6 +163,7 @@ def test_layout_parity_flux():
     G = gen.grid2d(30, 20, seed=3)
     _check_layout(G["edges"], G["n"], 64, G["geom"].astype(np.float32))
     _check_layout(G["edges"], G["n"], 64, G["geom"].astype(np.float32), order="input")
+    _check_layout(G["edges"], G["n"], 64, G["geom"].astype(np.float32), order="ggp")
     T = gen.tet_mesh(6, 5, 4, seed=3)
     _check_layout(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
 

@@ -299,3 +299,84 @@ def test_cpack_bipartite_classes():
     c = cost.partition_cost(E, n_x + n_y, part)
     tot = sum(info["nown"][cl] + len(info["foreign"][cl]) for info in lay["parts"] for cl in (0, 1))
     assert tot == c["loads"]
+
+
+# ---------------------------------------------------------------- multilevel (the EP order)
+
+from oracle import multilevel  # noqa: E402
+
+
+def test_multilevel_fig1(golden_dir):
+    G = _fig1(golden_dir)
+    E, n = np.array(G["edges"]), G["n"]
+    part, task, k = multilevel.partition(E, n, G["threads_per_block"])
+    assert k == 2
+    assert cost.partition_cost(E, n, part, k)["loads"] == G["ep_loads"] == 7
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(2, 40), st.integers(1, 150), st.integers(1, 40), st.integers(0, 10_000))
+def test_multilevel_invariants(n, m, cap, seed):
+    E = _random_graph(np.random.default_rng(seed), n, m)
+    part, task, k = multilevel.partition(E, n, cap)
+    assert k == math.ceil(m / (cap - cap // 20))
+    assert sorted(task.tolist()) == list(range(m))
+    assert part.min() >= 0 and part.max() < k
+    sizes = np.bincount(part, minlength=k)
+    assert sizes.max() <= cap  # hard capacity
+    pt = part[task]
+    assert (np.diff(pt) >= 0).all()  # parts in ascending order
+    for p in range(k):  # ascending edge id inside a part
+        ids = task[pt == p]
+        assert (np.diff(ids) > 0).all()
+    c = cost.partition_cost(E, n, part, k)
+    assert c["balance"] <= cap / (m / k) + 1e-12
+    assert c["cost"] <= c["aux_cut"]  # Theorem 1
+    assert c["loads"] == c["cost"] + c["n_active"]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_multilevel_not_below_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(3, 7))
+    m = int(rng.integers(3, 9))
+    cap = int(rng.integers(2, 5))
+    E = _random_graph(rng, n, m)
+    part, _, k = multilevel.partition(E, n, cap)
+    assert k == math.ceil(m / cap)  # cap < 20: no room below the capacity
+    c_star, _ = brute.min_edge_partition_cost(E, n, cap)
+    assert cost.partition_cost(E, n, part, k)["cost"] >= c_star
+
+
+@pytest.mark.parametrize("m,cap", [(10, 3), (64, 8), (200, 16), (1000, 40)])
+def test_multilevel_path_is_optimal(m, cap):
+    """A path split into q nonempty parts costs at least q - 1; contiguous arcs reach it."""
+    E = np.stack([np.arange(m), np.arange(1, m + 1)], axis=1)
+    part, _, k = multilevel.partition(E, m + 1, cap)
+    q = len(np.unique(part))
+    assert cost.partition_cost(E, m + 1, part, k)["cost"] == q - 1
+
+
+def test_multilevel_components_reach_zero():
+    cap = 6
+    rng = np.random.default_rng(4)
+    comps, base = [], 0
+    for _ in range(9):
+        comps.append(np.stack([np.arange(cap), np.arange(1, cap + 1)], 1) + base)
+        base += cap + 1
+    E = np.concatenate(comps)
+    E = rng.permutation(base)[E]
+    E = E[rng.permutation(len(E))]
+    part, _, k = multilevel.partition(E, base, cap)
+    assert cost.partition_cost(E, base, part, k)["cost"] == 0
+
+
+def test_multilevel_beats_single_pass_on_meshes():
+    """Not a pin of exact output: the multilevel order must not load more than greedy growing."""
+    import gen
+
+    for G in (gen.grid2d(40, 30, seed=2), gen.tet_mesh(10, 9, 8, seed=2)):
+        E, n = G["edges"], G["n"]
+        pm, _, k = multilevel.partition(E, n, 128)
+        pg, _ = ggp.partition(E, n, 128)
+        assert cost.partition_cost(E, n, pm, k)["loads"] < cost.partition_cost(E, n, pg)["loads"]
