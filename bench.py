@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+GRAPH_TIMING = False  # set by --graph
 CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
 
 
@@ -63,6 +64,8 @@ def _args():
     ap.add_argument("--cap", type=int, default=256)
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the K steps as one captured HIP graph (timing events inside the graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -122,13 +125,33 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1):
     gq = torch.empty_like(q)
     for _ in range(warmup):
         _step(P, torch, q, gr, r, gq, None)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        _step(P, torch, q, gr, r, gq, evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    if GRAPH_TIMING:
+        # the K timed steps, with timing events between the kernels, captured in one HIP graph
+        evs = [[torch.cuda.Event(enable_timing=True, external=True) for _ in range(5)] for _ in range(steps)]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            _step(P, torch, q, gr, r, gq, None)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for i in range(steps):
+                _step(P, torch, q, gr, r, gq, evs[i])
+        graph.replay()  # warm replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    else:
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            _step(P, torch, q, gr, r, gq, evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     names = ["flux_fwd", "reduce_fwd", "flux_bwd", "reduce_bwd"]
     dur = {nm: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, nm in enumerate(names)}
     step_gpu = float(np.mean([e[0].elapsed_time(e[4]) for e in evs]))
@@ -190,6 +213,8 @@ def cpu_baseline(G, budget_s):
 
 def main():
     args = _args()
+    global GRAPH_TIMING
+    GRAPH_TIMING = args.graph
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -251,6 +276,7 @@ def main():
                         f"(loss sum r^2), partitioned (EP) task order",
             "capacity": args.cap,
             "order": "ep",
+            "timing": "hip-graph replay of the timed steps" if args.graph else "eager launches",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
