@@ -12,9 +12,10 @@ GPU Caching Problems"):
 * ``graph``   - data-affinity graph, clone-and-connect transform, reconstruction
                 (Definitions 1, 3, 4).
 * ``cost``    - partition cost C, loads L and friends (Definition 2, Eq. 1).
-* ``ggp``     - the balanced vertex partition of the transformed graph, read as a
-                deterministic greedy graph-growing partitioner (Section 3.2; the
-                paper uses METIS, which is absent).
+* ``multilevel`` - the balanced vertex partition of the transformed graph
+                (Section 3.2; the paper uses METIS, which is absent), read as a
+                deterministic multilevel partitioner: the EP order.
+* ``ggp``     - the same step read as single-pass greedy graph growing.
 * ``cpack``   - first-touch data packing along the task order (Section 4.1).
 * ``flux``    - the cfd-style pairwise interaction, forward and adjoint (the
                 paper names the interaction's inputs in Section 3.1 but gives no
@@ -24,9 +25,10 @@ GPU Caching Problems"):
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
-CPU tests.  The exact output of ``ggp.partition`` and ``cpack.layout`` beyond
-those pins is parity unpinned: it is fixed by their specification and checked
-only by two independent implementations agreeing bit for bit.
+CPU tests.  The exact output of ``multilevel.partition``, ``ggp.partition``
+and ``cpack.layout`` beyond those pins is parity unpinned: it is fixed by
+their specification and checked only by two independent implementations
+agreeing bit for bit.
 """
 
 from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute  # noqa: F401
