@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 GRAPH_TIMING = False  # set by --graph
+COLD_STEPS = 10  # set by --cold-steps
 CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
 
 
@@ -66,6 +67,8 @@ def _args():
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
     ap.add_argument("--graph", action="store_true",
                     help="time the K steps as one captured HIP graph (timing events inside the graph)")
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="extra steps timed after a 1 GiB cache scrub each (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -125,9 +128,18 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1):
     gq = torch.empty_like(q)
     for _ in range(warmup):
         _step(P, torch, q, gr, r, gq, None)
+    # per-kernel durations: HIP events around every launch of K eager steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _step(P, torch, q, gr, r, gq, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    graph_ms = None
     if GRAPH_TIMING:
-        # the K timed steps, with timing events between the kernels, captured in one HIP graph
-        evs = [[torch.cuda.Event(enable_timing=True, external=True) for _ in range(5)] for _ in range(steps)]
+        # the K steps captured in one HIP graph (no events inside: ROCm refuses external events),
+        # timed by events around its replay
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -137,23 +149,31 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1):
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             for i in range(steps):
-                _step(P, torch, q, gr, r, gq, evs[i])
+                _step(P, torch, q, gr, r, gq, None)
         graph.replay()  # warm replay
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        g0.record()
         graph.replay()
+        g1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-    else:
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(steps):
-            _step(P, torch, q, gr, r, gq, evs[i])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        graph_ms = g0.elapsed_time(g1) / steps
     names = ["flux_fwd", "reduce_fwd", "flux_bwd", "reduce_bwd"]
     dur = {nm: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, nm in enumerate(names)}
+    cold = None
+    if COLD_STEPS > 0:
+        # cold caches: a 1 GiB read-modify-write between steps evicts L2 and MALL (256 MiB)
+        scrub = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+        cev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(COLD_STEPS)]
+        for i in range(COLD_STEPS):
+            scrub.add_(1.0)
+            _step(P, torch, q, gr, r, gq, cev[i])
+        torch.cuda.synchronize()
+        del scrub
+        cold = {nm: float(np.median([e[i].elapsed_time(e[i + 1]) for e in cev])) for i, nm in enumerate(names)}
+        cold["step"] = float(np.median([e[0].elapsed_time(e[4]) for e in cev]))
     step_gpu = float(np.mean([e[0].elapsed_time(e[4]) for e in evs]))
     info = P.info()
     st = P.stats
@@ -168,6 +188,8 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1):
         "plan_seconds": plan_s,
         "bytes_per_edge_fwd_bwd": (info["bytes_fwd"] + info["bytes_bwd"]) / m,
         "edges_per_s": m / (wall / steps),
+        "cold_ms": cold,
+        "graph_gpu_ms_per_step": graph_ms,
     }
 
 
@@ -197,24 +219,52 @@ def cpu_baseline(G, budget_s):
         t_small = time.perf_counter() - t0
         per_edge = t_small / m_s
         m_s = int(min(m_all, max(m_s, budget_s / max(per_edge, 1e-12))))
+        # the whole workload when it fits the budget, repeated to fill about half of it
+        reps = max(1, int(0.5 * budget_s / (per_edge * m_s))) if m_s == m_all else 1
         E = G["edges"][:m_s]
         t0 = time.perf_counter()
-        flux.forward(G["n"], E, geom[:m_s], q)
-        flux.backward(G["n"], E, geom[:m_s], q, gr)
+        for _ in range(reps):
+            flux.forward(G["n"], E, geom[:m_s], q)
+            flux.backward(G["n"], E, geom[:m_s], q, gr)
         t = time.perf_counter() - t0
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    return {"value": m_s / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m_s} of {m_all} edges (all {G['n']} cells' states), FP64 forward + adjoint, "
+    what = f"all {m_all} edges x {reps} passes" if m_s == m_all else f"first {m_s} of {m_all} edges"
+    return {"value": reps * m_s / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} (all {G['n']} cells' states), FP64 forward + adjoint, "
                       f"{t:.1f} s on {platform.processor() or platform.machine()} "
                       f"(host reports {os.cpu_count()} CPUs; 1 thread used)"}
 
 
+def cpu_baseline_spmv(R, budget_s):
+    """The FP64 oracle SpMV (numpy bincount, one thread) over the whole R-MAT matrix, repeated."""
+    from threadpoolctl import threadpool_limits
+
+    from gen.rmat import spmv_graph
+    from oracle import spmv
+
+    g = spmv_graph(R, R["shuffle"])
+    m = len(g["edges"])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+        t1 = time.perf_counter() - t0
+        reps = max(1, int(0.5 * budget_s / t1))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+        t = time.perf_counter() - t0
+    return {"value": reps * m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {m} nonzeros x {reps} passes, FP64, {t:.1f} s on "
+                      f"{platform.processor() or platform.machine()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
+
+
 def main():
     args = _args()
-    global GRAPH_TIMING
+    global GRAPH_TIMING, COLD_STEPS
     GRAPH_TIMING = args.graph
+    COLD_STEPS = args.cold_steps
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -283,6 +333,8 @@ def main():
                      "traffic": traffic["ep"][dom]["bytes"] if traffic else None},
         "kernels": per_kernel,
         "gpu_ms_per_step": ep["gpu_ms_per_step"],
+        "cold_ms": {"ep": ep["cold_ms"], "default": default["cold_ms"] if default else None,
+                    "protocol": "median over steps, each after a 1 GiB read-modify-write scrub"},
         "algorithmic_bytes_per_edge": {"ep": ep["bytes_per_edge_fwd_bwd"]},
         "partition": {"loads_per_edge": st["loads"] / m, "cost": st["cost"], "replicated": st["replicated"],
                       "slots": st["slots"], "balance": st["balance"], "n_parts": st["n_parts"],
@@ -375,7 +427,7 @@ def bench_spmv(args, torch):
                        "frac": ach / HBM_PEAK_GBS, "traffic": None}
     out["orders"] = res
     out["source_sha256"] = source_sha256()
-    out["cpu_baseline"] = None
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s)
     print(json.dumps(out), flush=True)
 
 
@@ -441,8 +493,33 @@ def bench_batch(args, torch):
                     "caps": {int(c): int((caps == c).sum()) for c in np.unique(caps)}, "gpu_ms_per_step": gpu_ms,
                     "algorithmic_bytes_per_step": algo, "gen_s": gen_s, "autotune_s": tune_s, "plan_s": plan_s}
     out["source_sha256"] = source_sha256()
-    out["cpu_baseline"] = None
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_batch(graphs, args.cpu_budget_s)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(graphs, budget_s):
+    """The FP64 oracle forward + adjoint (numpy, one thread) over the leading graphs of the batch."""
+    from threadpoolctl import threadpool_limits
+
+    import gen
+    from oracle import flux
+
+    done_m, t = 0, 0.0
+    with threadpool_limits(1):
+        for i, g in enumerate(graphs):
+            q = gen.flux_state(g["n"], seed=i).astype(np.float64)
+            gr = gen.workloads.grad_seed(g["n"], seed=i).astype(np.float64)
+            geom = g["geom"].astype(np.float32).astype(np.float64)
+            t0 = time.perf_counter()
+            flux.forward(g["n"], g["edges"], geom, q)
+            flux.backward(g["n"], g["edges"], geom, q, gr)
+            t += time.perf_counter() - t0
+            done_m += len(g["edges"])
+            if t > 0.5 * budget_s:
+                break
+    return {"value": done_m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"graphs 0..{i} of {len(graphs)} ({done_m} edges), FP64 forward + adjoint, {t:.1f} s on "
+                      f"{platform.processor() or platform.machine()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
 
 
 if __name__ == "__main__":

@@ -80,7 +80,10 @@ typedef struct {
 
 /* A data-affinity graph (Definition 1).
  * FLUX5: edge e = (u, v), geometry = the unit normal from u to v (+ area):
- *        geom_ncomp 2 -> (nx, ny), area 1;  4 -> (nx, ny, nz, area).
+ *        geom_ncomp 2 -> (nx, ny), area 1;  4 -> (nx, ny, nz, area).  The
+ *        plan stores 3D geometry as the area vector area*(nx, ny, nz) (the
+ *        Euler normal flux is linear in the normal) and recovers the area as
+ *        its length; the normal must therefore have unit length.
  * SPMV : vertices [0, n_x) are x, [n_x, n_vertices) are y; edge e must be
  *        (j, n_x + i) for nonzero A[i][j]; geom_ncomp 1 -> the weight A[i][j].
  * edge_uv is host [n_edges][2], edge_geom host [n_edges][geom_ncomp].      */

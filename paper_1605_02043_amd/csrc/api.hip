@@ -136,7 +136,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
       hdr.push_back(hq[7]);
     }
     eloc.insert(eloc.end(), hptr<uint32_t>(p, L.eloc), hptr<uint32_t>(p, L.eloc) + p->m);
-    geom.insert(geom.end(), hptr<float>(p, L.geom), hptr<float>(p, L.geom) + 4 * p->m);
+    geom.insert(geom.end(), hptr<float>(p, L.geom), hptr<float>(p, L.geom) + 3 * p->m);
     inc.insert(inc.end(), hptr<uint16_t>(p, L.inc), hptr<uint16_t>(p, L.inc) + 2 * p->m);
     loff.insert(loff.end(), hptr<uint16_t>(p, L.loff), hptr<uint16_t>(p, L.loff) + nloff);
     for (int64_t i = 0; i < C; ++i) fid.push_back(int32_t(hptr<int32_t>(p, L.fid)[i] + voff));

@@ -36,7 +36,9 @@ int grid_of_parts(int k, int swizzle) { return swizzle ? 8 * ((k + 7) / 8) : k; 
 
 // ------------------------------------------------------------------ FLUX5
 
-// Edge flux a * F(q_u, q_v, n) of the cfd-style interaction.
+// Edge flux a * F(q_u, q_v, n) of the cfd-style interaction, evaluated from
+// the area vector A = a n: the Euler normal flux is linear in the normal, so
+// a f(q, n) = f(q, A), and only the dissipation term needs a = |A| itself.
 __device__ __forceinline__ void edge_flux(const float *qu, const float *qv, float n1, float n2, float n3, float a,
                                           float F[5]) {
   float fu[5], fv[5];
@@ -56,7 +58,7 @@ __device__ __forceinline__ void edge_flux(const float *qu, const float *qv, floa
     f[4] = (E + p) * s;
   }
 #pragma unroll
-  for (int c = 0; c < 5; ++c) F[c] = a * (0.5f * (fu[c] + fv[c]) - 0.5f * kSigma * (qv[c] - qu[c]));
+  for (int c = 0; c < 5; ++c) F[c] = 0.5f * (fu[c] + fv[c]) - (0.5f * kSigma * a) * (qv[c] - qu[c]);
 }
 
 // Vector-Jacobian product of the Euler normal flux: out = J(q, n)^T d.
@@ -81,14 +83,15 @@ __device__ __forceinline__ void euler_vjp(const float *q, float n1, float n2, fl
   out[4] = B * kG1 + d[4] * s;
 }
 
+// 3D edges carry the area vector A = a n (3 floats); 2D edges the unit normal (a = 1).
 template <int G>
 __device__ __forceinline__ void load_geom(const float *geom, int64_t e, float &n1, float &n2, float &n3, float &a) {
   if constexpr (G == 4) {
-    const float4 g = reinterpret_cast<const float4 *>(geom)[e];
-    n1 = g.x;
-    n2 = g.y;
-    n3 = g.z;
-    a = g.w;
+    const float *g = geom + 3 * e;
+    n1 = g[0];
+    n2 = g[1];
+    n3 = g[2];
+    a = sqrtf(n1 * n1 + n2 * n2 + n3 * n3);
   } else {
     const float2 g = reinterpret_cast<const float2 *>(geom)[e];
     n1 = g.x;
@@ -267,16 +270,17 @@ __device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const 
     const int j = tid + k * nt;
     if (j < h.ne) {
       const int lu = ew[k] & 0xffffu, lv = ew[k] >> 16;
-      const float a = eg[k].w;
+      // d(a F)/dq = a J(q, n) / 2 +- a sigma I / 2 = J(q, A) / 2 +- a sigma I / 2 (J linear in n)
+      const float hs = 0.5f * kSigma * eg[k].w;
       float d[5], ju[5], jv[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) d[c] = a * (gs[lu * 5 + c] - gs[lv * 5 + c]);
+      for (int c = 0; c < 5; ++c) d[c] = gs[lu * 5 + c] - gs[lv * 5 + c];
       euler_vjp(st + lu * 5, eg[k].x, eg[k].y, eg[k].z, d, ju);
       euler_vjp(st + lv * 5, eg[k].x, eg[k].y, eg[k].z, d, jv);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        vu[j * 5 + c] = 0.5f * ju[c] + 0.5f * kSigma * d[c];
-        vv[j * 5 + c] = 0.5f * jv[c] - 0.5f * kSigma * d[c];
+        vu[j * 5 + c] = 0.5f * ju[c] + hs * d[c];
+        vv[j * 5 + c] = 0.5f * jv[c] - hs * d[c];
       }
     }
   }

@@ -163,7 +163,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->foreign_ids.reserve(size_t(P->stats.cost));
     std::vector<int32_t> stamp(size_t(n), -1), loc(size_t(n), 0);
     std::vector<uint32_t> eloc(static_cast<size_t>(m));
-    std::vector<float> geomk(size_t(m) * size_t(g->geom_ncomp));
+    // 3D flux geometry (n, a) is stored as the area vector A = a n: 3 floats per edge
+    const int gstore = (kind == EPK_FLUX5 && g->geom_ncomp == 4) ? 3 : g->geom_ncomp;
+    std::vector<float> geomk(size_t(m) * size_t(gstore));
     std::vector<int32_t> hdr(size_t(k) * kHdrInts, 0);
     std::vector<uint16_t> incl, loff;
     if (kind == EPK_FLUX5) {
@@ -225,8 +227,12 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
           const int32_t e = P->task[pos + j];
           const uint32_t lu = local(uv[2 * size_t(e)]), lv = local(uv[2 * size_t(e) + 1]);
           eloc[e0 + j] = lu | (lv << 16);
-          std::memcpy(&geomk[size_t(e0 + j) * g->geom_ncomp], &g->edge_geom[size_t(e) * g->geom_ncomp],
-                      sizeof(float) * g->geom_ncomp);
+          const float *ge = &g->edge_geom[size_t(e) * g->geom_ncomp];
+          float *gk = &geomk[size_t(e0 + j) * gstore];
+          if (gstore == 3)
+            for (int c = 0; c < 3; ++c) gk[c] = ge[c] * ge[3];
+          else
+            std::memcpy(gk, ge, sizeof(float) * gstore);
           cnt[lu + 1]++;
           cnt[lv + 1]++;
         }
@@ -355,7 +361,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->lds_fwd = flux_fwd_lds(P->max_u, cap, false);
       P->lds_fwd_qn = flux_fwd_lds(P->max_u, cap, true);
       P->lds_bwd = flux_bwd_lds(P->max_u, cap);
-      const int64_t G = g->geom_ncomp, na = P->n_active_out;
+      const int64_t G = gstore, na = P->n_active_out;
       const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
       P->bytes_bwd_kernel = meta + 40 * Lds + 20 * na + 20 * C;
