@@ -134,7 +134,10 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s);
  * [2] = of the adjoint, [3] = workgroup size, [4] = vertex classes,
  * [5] = algorithmic HBM bytes of one forward (fwd + reduce),
  * [6] = algorithmic HBM bytes of one adjoint (bwd + reduce),
- * [7] = forward-kernel-only bytes, [8] = adjoint-kernel-only bytes.        */
+ * [7] = forward-kernel-only bytes, [8] = adjoint-kernel-only bytes,
+ * [9] = max foreign vertices of a part, [10] = pipelined launch setting
+ * (0: off), [11] / [12] = its forward / adjoint grid, [13] = its adjoint
+ * LDS bytes.                                                              */
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
  * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
@@ -142,6 +145,17 @@ int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
  * (x+1)*ceil(k/8)), so parts sharing vertices share an L2; 0: part =
  * workgroup id; -1 keeps the current one).  Host only.                   */
 int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle);
+/* FLUX5 only: run the part kernels as a software-pipelined persistent
+ * launch.  A grid of blocks_per_cu workgroups per CU (-1: as many as fit;
+ * 0: back to one workgroup per part) walks the parts; each workgroup loads
+ * the header, foreign ids and rows of its next parts while it computes the
+ * current one, so the three dependent loads of a part (Section 4's
+ * per-block staging) overlap the work of others.  Results are bitwise those
+ * of the one-part-per-workgroup launch.  Needs wg <= 256 and the current
+ * device (the grid is sized from its CU count and the kernels' occupancy);
+ * epk_plan_set_launch switches it off again.  EPK_ERANGE if the double
+ * buffers do not fit in a workgroup's LDS.                                */
+int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
 void epk_plan_destroy(epk_plan *p);
 
 /* ---------------------------------------------------------------- device */
@@ -181,15 +195,18 @@ int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n
  * rows [vertex_offset(g), vertex_offset(g) + n_g) of one [sum n][5] array,
  * in graph g's packed order.  The plans must be FLUX5 with 4 geometry
  * components; the batch copies what it needs, the plans may be destroyed.
- * Work items (graph, part) are taken from a device-side queue in
- * decreasing size; the queue resets itself at the end of every launch.   */
+ * Work items (graph, part) are dealt round-robin, largest first, to the
+ * workgroups of one pipelined persistent launch (see
+ * epk_plan_set_pipeline); the grid is fixed at upload.                    */
 int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out);
 int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes);
-/* Copy the image (including a zeroed queue counter) to d_image.          */
+/* Copy the image to d_image and size the grids for the current device.   */
 int epk_batch_upload(epk_batch *b, void *d_image, void *stream);
 /* vertex_offset[n_graphs + 1] (rows), total in [n_graphs].               */
 int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset);
-/* [0] items, [1] grid, [2] LDS bytes, [3] algorithmic bytes of one forward. */
+/* [0] items, [1] forward grid, [2] forward LDS bytes, [3] / [4] algorithmic
+ * bytes of one forward / adjoint, [5] workgroup size, [6] edges,
+ * [7] adjoint grid.                                                       */
 int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info);
 int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream);
 int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws,

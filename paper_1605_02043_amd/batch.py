@@ -41,9 +41,9 @@ class Batch:
         return a.value, b.value
 
     def info(self) -> dict:
-        a = np.zeros(7, dtype=np.int64)
-        check(lib.epk_batch_info(self._h, i64p(a), 7))
-        return dict(zip(["items", "grid", "lds_fwd", "bytes_fwd", "bytes_bwd", "wg", "m"], a.tolist()))
+        a = np.zeros(8, dtype=np.int64)
+        check(lib.epk_batch_info(self._h, i64p(a), 8))
+        return dict(zip(["items", "grid", "lds_fwd", "bytes_fwd", "bytes_bwd", "wg", "m", "grid_bwd"], a.tolist()))
 
     def upload(self, device="cuda"):
         import torch

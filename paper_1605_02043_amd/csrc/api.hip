@@ -37,9 +37,7 @@ DevPlan dev_plan(const epk_plan *p) {
   P.roff = dptr<int32_t>(b, L.roff);
   P.rslot = dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
-  P.items = nullptr;
   P.iso = nullptr;
-  P.queue = nullptr;
   P.m = p->m;
   P.k = int32_t(p->k);
   P.cap = p->cap;
@@ -50,7 +48,7 @@ DevPlan dev_plan(const epk_plan *p) {
   P.n_heavy = int32_t(p->n_heavy);
   P.max_u = int32_t(p->max_u);
   P.max_uy = int32_t(p->max_uy);
-  P.grid = 0;
+  P.max_nf = int32_t(p->max_nf);
   P.n_iso = 0;
   return P;
 }
@@ -70,9 +68,7 @@ DevPlan dev_batch(const epk_batch *bt) {
   P.roff = dptr<int32_t>(b, L.roff);
   P.rslot = dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
-  P.items = dptr<int32_t>(b, L.items);
   P.iso = dptr<int32_t>(b, L.iso);
-  P.queue = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b) + L.queue);
   P.m = bt->m;
   P.k = int32_t(bt->k);
   P.cap = int32_t(bt->max_cap);
@@ -83,9 +79,17 @@ DevPlan dev_batch(const epk_batch *bt) {
   P.n_heavy = int32_t(bt->n_heavy);
   P.max_u = int32_t(bt->max_u);
   P.max_uy = 0;
-  P.grid = int32_t(bt->grid);
+  P.max_nf = int32_t(bt->max_nf);
   P.n_iso = int32_t(bt->n_iso);
   return P;
+}
+
+// Grid of a pipelined launch: per_cu workgroups on each of cus CUs, at most
+// one per part, a multiple of 8 under the XCD-aware part lists.
+static int64_t pipe_grid(int cus, int per_cu, int64_t k, bool swizzle) {
+  int64_t g = std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, k));
+  if (swizzle) g = (g + 7) / 8 * 8;
+  return g;
 }
 
 static int hip_status(hipError_t e, const char *what) {
@@ -112,7 +116,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   epk_batch *B = new epk_batch();
   B->n_graphs = n_graphs;
   B->voff.assign(size_t(n_graphs) + 1, 0);
-  std::vector<int32_t> hdr, fid, rvid, roff(1, 0), rslot, heavy, iso, items;
+  std::vector<int32_t> hdr, fid, rvid, roff(1, 0), rslot, heavy, iso;
   std::vector<uint32_t> eloc;
   std::vector<float> geom;
   std::vector<uint16_t> inc, loff;
@@ -149,6 +153,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     for (int64_t v = p->n_active_out; v < p->n_out; ++v) iso.push_back(int32_t(v + voff));
     B->voff[g + 1] = voff + p->n;
     B->max_u = std::max<int64_t>(B->max_u, p->max_u);
+    B->max_nf = std::max<int64_t>(B->max_nf, p->max_nf);
     B->max_cap = std::max<int64_t>(B->max_cap, p->cap);
     B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce;
     B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce;
@@ -167,14 +172,22 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     delete B;
     return fail(EPK_ERANGE, "batch too large for 32-bit ids");
   }
-  // largest parts first (ties: lower id first)
-  items.resize(size_t(B->k));
-  for (int64_t i = 0; i < B->k; ++i) items[i] = int32_t(i);
-  std::stable_sort(items.begin(), items.end(),
-                   [&](int32_t a, int32_t b) { return hdr[size_t(a) * kHdrInts + 1] > hdr[size_t(b) * kHdrInts + 1]; });
+  // headers in processing order: largest parts first (ties: lower id first);
+  // the pipelined kernel deals them round-robin over its workgroups
+  {
+    std::vector<int32_t> order(static_cast<size_t>(B->k));
+    for (int64_t i = 0; i < B->k; ++i) order[i] = int32_t(i);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return hdr[size_t(a) * kHdrInts + 1] > hdr[size_t(b) * kHdrInts + 1];
+    });
+    std::vector<int32_t> sorted(hdr.size());
+    for (int64_t i = 0; i < B->k; ++i)
+      std::memcpy(&sorted[size_t(i) * kHdrInts], &hdr[size_t(order[i]) * kHdrInts], sizeof(int32_t) * kHdrInts);
+    hdr.swap(sorted);
+  }
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
-  B->lds_fwd = flux_fwd_lds(B->max_u, B->max_cap, false);
-  B->lds_bwd = flux_bwd_lds(B->max_u, B->max_cap);
+  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false);
+  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false);
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");
@@ -196,9 +209,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   L.roff = take(roff.size() * 4);
   L.rslot = take(rslot.size() * 4);
   L.heavy = take(heavy.size() * 4);
-  L.items = take(items.size() * 4);
   L.iso = take(iso.size() * 4);
-  L.queue = take(16);
   L.total = off;
   B->image.assign(L.total, 0);
   auto put = [&](size_t o, const void *src, size_t bytes) {
@@ -214,7 +225,6 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   put(L.roff, roff.data(), roff.size() * 4);
   put(L.rslot, rslot.data(), rslot.size() * 4);
   put(L.heavy, heavy.data(), heavy.size() * 4);
-  put(L.items, items.data(), items.size() * 4);
   put(L.iso, iso.data(), iso.size() * 4);
   B->ws_bytes = align256(std::max<size_t>(size_t(foff) * 5 * 4, 4));
   *out = B;
@@ -295,6 +305,34 @@ int epk_plan_upload(epk_plan *p, void *d_image, void *stream) {
   return EPK_OK;
 }
 
+int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (blocks_per_cu < -1) return fail(EPK_EINVAL, "blocks_per_cu must be -1, 0 or positive");
+  if (blocks_per_cu == 0) {
+    p->pipe = 0;
+    return EPK_OK;
+  }
+  if (p->kind != EPK_FLUX5) return fail(EPK_EINVAL, "the pipelined launch is for FLUX5 plans");
+  if (p->wg > 256) return fail(EPK_EINVAL, "the pipelined launch needs a workgroup of at most 256");
+  if (p->lds_pipe_fwd_qn > kMaxLdsBytes || p->lds_pipe_bwd > kMaxLdsBytes)
+    return fail(EPK_ERANGE, "parts too large for the pipelined launch's LDS buffers");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_status(e, "CU count");
+  const int G = p->geom_ncomp;
+  const int occ[3] = {pipe_blocks_per_cu(p->wg, size_t(p->lds_pipe_fwd), false, G, false, p->cap),
+                      pipe_blocks_per_cu(p->wg, size_t(p->lds_pipe_fwd_qn), false, G, true, p->cap),
+                      pipe_blocks_per_cu(p->wg, size_t(p->lds_pipe_bwd), true, G, false, p->cap)};
+  auto per = [&](int o) { return blocks_per_cu < 0 ? o : std::min(o, int(blocks_per_cu)); };
+  p->grid_pipe_fwd = pipe_grid(cus, per(occ[0]), p->k, p->swizzle);
+  p->grid_pipe_fwd_qn = pipe_grid(cus, per(occ[1]), p->k, p->swizzle);
+  p->grid_pipe_bwd = pipe_grid(cus, per(occ[2]), p->k, p->swizzle);
+  p->pipe = blocks_per_cu;
+  return EPK_OK;
+}
+
 static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                      float dt, float *q_new, void *d_ws, void *stream) {
   if (!p) return fail(EPK_EINVAL, "plan is NULL");
@@ -316,7 +354,15 @@ static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *
   if (op == EPK_OP_BACKWARD) q_new = nullptr;
   if (stage != 1) {  // -1 runs both
     hipError_t e = hipSuccess;
-    if (op == EPK_OP_FORWARD)
+    if (op != EPK_OP_SPMV && p->pipe) {
+      if (op == EPK_OP_FORWARD)
+        e = launch_flux_pipe(P, p->wg, int(q_new ? p->grid_pipe_fwd_qn : p->grid_pipe_fwd),
+                             size_t(q_new ? p->lds_pipe_fwd_qn : p->lds_pipe_fwd), in, nullptr, out, q_new, dt, ws,
+                             false, p->swizzle, s);
+      else
+        e = launch_flux_pipe(P, p->wg, int(p->grid_pipe_bwd), size_t(p->lds_pipe_bwd), in, g_r, out, nullptr, 0.f, ws,
+                             true, p->swizzle, s);
+    } else if (op == EPK_OP_FORWARD)
       e = launch_flux_fwd(P, p->wg, size_t(q_new ? p->lds_fwd_qn : p->lds_fwd), in, out, q_new, dt, ws, p->swizzle, s);
     else if (op == EPK_OP_BACKWARD)
       e = launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), in, g_r, out, ws, p->swizzle, s);
@@ -392,9 +438,10 @@ int epk_batch_upload(epk_batch *b, void *d_image, void *stream) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_status(e, "CU count");
-  const int per_cu = std::min(persistent_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false, int(b->max_cap)),
-                              persistent_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true, int(b->max_cap)));
-  b->grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, b->k));
+  b->grid_fwd = pipe_grid(cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false, 4, false, int(b->max_cap)),
+                          b->k, false);
+  b->grid_bwd = pipe_grid(cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true, 4, false, int(b->max_cap)),
+                          b->k, false);
   e = hipMemcpyAsync(d_image, b->image.data(), b->lay.total, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_status(e, "batch upload");
   b->d_image = d_image;
@@ -411,8 +458,8 @@ int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset) {
 int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info) {
   clear_error();
   if (!b || !info) return fail(EPK_EINVAL, "NULL argument");
-  const int64_t v[7] = {b->k, b->grid, b->lds_fwd, b->bytes_fwd, b->bytes_bwd, b->wg, b->m};
-  for (int32_t i = 0; i < n_info && i < 7; ++i) info[i] = v[i];
+  const int64_t v[8] = {b->k, b->grid_fwd, b->lds_fwd, b->bytes_fwd, b->bytes_bwd, b->wg, b->m, b->grid_bwd};
+  for (int32_t i = 0; i < n_info && i < 8; ++i) info[i] = v[i];
   return EPK_OK;
 }
 
@@ -423,8 +470,8 @@ int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, 
   if (b->n > 0 && (!q || !r || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
   const DevPlan P = dev_batch(b);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_persistent(P, int(b->wg), size_t(b->lds_fwd), q, nullptr, r, static_cast<float *>(d_ws),
-                                        false, s);
+  hipError_t e = launch_flux_pipe(P, int(b->wg), int(b->grid_fwd), size_t(b->lds_fwd), q, nullptr, r, nullptr, 0.f,
+                                  static_cast<float *>(d_ws), false, 0, s);
   if (e != hipSuccess) return hip_status(e, "batch forward launch");
   return hip_status(launch_reduce(P, 5, r, static_cast<const float *>(d_ws), q, nullptr, 0.f, s), "reduce launch");
 }
@@ -436,8 +483,8 @@ int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, flo
   if (b->n > 0 && (!q || !g_r || !g_q || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
   const DevPlan P = dev_batch(b);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_persistent(P, int(b->wg), size_t(b->lds_bwd), q, g_r, g_q, static_cast<float *>(d_ws),
-                                        true, s);
+  hipError_t e = launch_flux_pipe(P, int(b->wg), int(b->grid_bwd), size_t(b->lds_bwd), q, g_r, g_q, nullptr, 0.f,
+                                  static_cast<float *>(d_ws), true, 0, s);
   if (e != hipSuccess) return hip_status(e, "batch adjoint launch");
   return hip_status(launch_reduce(P, 5, g_q, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s),
                     "reduce launch");

@@ -46,7 +46,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
-  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, queue = 0, items = 0, iso = 0, eoff = 0;
+  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
   size_t total = 0;
 };
 
@@ -62,10 +62,8 @@ struct DevPlan {
   const int32_t *roff;
   const int32_t *rslot;
   const int32_t *heavy;
-  const int32_t *items;  // batch: part ids in processing order
   const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
   const int32_t *eoff;   // [k + 1] first task of every part
-  uint32_t *queue;       // batch: [0] ticket counter, [1] exit counter
   int64_t m;
   int32_t k;
   int32_t cap;
@@ -76,7 +74,7 @@ struct DevPlan {
   int32_t n_heavy;
   int32_t max_u;      // max vertices per part (FLUX5) / max x vertices per part (SPMV)
   int32_t max_uy;     // SPMV: max y vertices per part
-  int32_t grid;       // batch: persistent grid size
+  int32_t max_nf;     // max foreign vertices per part
   int32_t n_iso;      // batch: entries of iso
 };
 
@@ -95,7 +93,12 @@ struct epk_plan {
   epk::ImageLayout lay;
   size_t ws_bytes = 0;
   int64_t R = 0, n_heavy = 0, n_active_out = 0, n_out = 0, max_u = 0, max_uy = 0;
-  int64_t lds_fwd = 0, lds_fwd_qn = 0, lds_bwd = 0, n_loff = 0;
+  int64_t lds_fwd = 0, lds_fwd_qn = 0, lds_bwd = 0, n_loff = 0, max_nf = 0;
+  // pipelined persistent launch (FLUX5): workgroups per CU asked for (0: one
+  // workgroup per part), LDS bytes and grid sizes of the three kernels
+  int32_t pipe = 0;
+  int64_t lds_pipe_fwd = 0, lds_pipe_fwd_qn = 0, lds_pipe_bwd = 0;
+  int64_t grid_pipe_fwd = 0, grid_pipe_fwd_qn = 0, grid_pipe_bwd = 0;
   int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
   void *d_image = nullptr;
 };
@@ -107,7 +110,8 @@ struct epk_batch {
   std::vector<uint8_t> image;
   epk::ImageLayout lay;
   size_t ws_bytes = 0;
-  int64_t R = 0, n_heavy = 0, n_iso = 0, max_u = 0, max_cap = 0, grid = 0, wg = 256;
+  int64_t R = 0, n_heavy = 0, n_iso = 0, max_u = 0, max_nf = 0, max_cap = 0, wg = 256;
+  int64_t grid_fwd = 0, grid_bwd = 0;  // pipelined persistent grids
   int64_t lds_fwd = 0, lds_bwd = 0, bytes_fwd = 0, bytes_bwd = 0;
   void *d_image = nullptr;
 };
@@ -116,6 +120,7 @@ namespace epk {
 // LDS bytes of the FLUX5 kernels for a given part shape (must match the kernels' carve-up).
 int64_t flux_fwd_lds(int64_t max_u, int64_t cap, bool qnew);
 int64_t flux_bwd_lds(int64_t max_u, int64_t cap);
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew);
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
 DevPlan dev_plan(const epk_plan *p);

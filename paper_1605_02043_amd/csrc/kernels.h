@@ -12,15 +12,15 @@ hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q,
                            float *ws, int swizzle, hipStream_t s);
 hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
                            int swizzle, hipStream_t s);
-hipError_t launch_flux_persistent(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
-                                  float *ws, bool backward, hipStream_t s);
+hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, const float *q, const float *gr,
+                            float *out, float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s);
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
                        hipStream_t s);
 hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, const float *q, float *qn, float dt,
                          hipStream_t s);
 hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int ncomp, int inverse,
                           hipStream_t s);
-int persistent_blocks_per_cu(int wg, size_t lds, bool backward, int cap);
+int pipe_blocks_per_cu(int wg, size_t lds, bool backward, int G, bool qnew, int cap);
 int edges_per_thread(int cap, int wg);
 
 }  // namespace epk

@@ -83,29 +83,31 @@ __device__ __forceinline__ void euler_vjp(const float *q, float n1, float n2, fl
   out[4] = B * kG1 + d[4] * s;
 }
 
-// 3D edges carry the area vector A = a n (3 floats); 2D edges the unit normal (a = 1).
+// 3D edges carry the area vector A = a n (3 floats); 2D edges the unit normal.
 template <int G>
-__device__ __forceinline__ void load_geom(const float *geom, int64_t e, float &n1, float &n2, float &n3, float &a) {
+__device__ __forceinline__ float4 load_geom(const float *geom, int64_t e) {
   if constexpr (G == 4) {
     const float *g = geom + 3 * e;
-    n1 = g[0];
-    n2 = g[1];
-    n3 = g[2];
-    a = sqrtf(n1 * n1 + n2 * n2 + n3 * n3);
+    return make_float4(g[0], g[1], g[2], 0.f);
   } else {
     const float2 g = reinterpret_cast<const float2 *>(geom)[e];
-    n1 = g.x;
-    n2 = g.y;
-    n3 = 0.0f;
-    a = 1.0f;
+    return make_float4(g.x, g.y, 0.f, 0.f);
   }
+}
+
+// The face area: |A| in 3D, 1 in 2D.  Evaluated once the loads have landed,
+// so that no arithmetic sits between a load and the next one.
+template <int G>
+__device__ __forceinline__ float geom_area(const float4 &g) {
+  if constexpr (G == 4)
+    return sqrtf(g.x * g.x + g.y * g.y + g.z * g.z);
+  else
+    return 1.0f;
 }
 
 // ------------------------------------------------------------------ staging
 
 #define EPK_LDS(p) ((__attribute__((address_space(3))) void *)(p))
-
-constexpr int kMaxFI = 16;  // foreign-state dwords prefetched per thread (covers 16 * wg / 5 vertices)
 
 // Copy src[0, n) to LDS dst[0, n) with direct-to-LDS loads: lane l of a wave
 // writes its dword at (wave base + 4 l); the base d - lane is wave-uniform
@@ -115,33 +117,37 @@ __device__ __forceinline__ void dma_block(float *dst, const float *src, int n, i
   for (int d = tid; d < n; d += nt) __builtin_amdgcn_global_load_lds(src + d, EPK_LDS(dst + (d - lane)), 4, 0, 0);
 }
 
-// Stage 5 * nf foreign state dwords: every foreign id is read first (one batch
-// of independent loads), then the states are fetched straight into LDS.
-__device__ __forceinline__ void dma_foreign(float *dst, const float *__restrict__ src, const int32_t *__restrict__ fids,
-                                            int nf, int tid, int nt) {
+// Stage NC * nf dwords of the rows src[ids[i]] (ids already in LDS) into
+// dst[i][NC].  Two ids are read per pass so that their LDS reads overlap.
+template <int NC>
+__device__ __forceinline__ void dma_rows(float *dst, const float *__restrict__ src, const int32_t *ids, int nf, int tid,
+                                         int nt) {
   const int lane = tid & 63;
-  const int nfd = nf * 5;
-  int fr[kMaxFI];
-#pragma unroll
-  for (int k = 0; k < kMaxFI; ++k) {
-    const int d = tid + k * nt;
-    fr[k] = d < nfd ? fids[d / 5] : 0;
-  }
-#pragma unroll
-  for (int k = 0; k < kMaxFI; ++k) {
-    const int d = tid + k * nt;
-    if (d < nfd)
-      __builtin_amdgcn_global_load_lds(src + int64_t(fr[k]) * 5 + (d - 5 * (d / 5)), EPK_LDS(dst + (d - lane)), 4, 0, 0);
-  }
-  for (int d = tid + kMaxFI * nt; d < nfd; d += nt)  // parts wider than the prefetch window
-    __builtin_amdgcn_global_load_lds(src + int64_t(fids[d / 5]) * 5 + (d - 5 * (d / 5)), EPK_LDS(dst + (d - lane)), 4,
+  const int nd = nf * NC;
+  int d = tid;
+  for (; d + nt < nd; d += 2 * nt) {
+    const int v0 = d / NC, v1 = (d + nt) / NC;
+    const int i0 = ids[v0], i1 = ids[v1];
+    __builtin_amdgcn_global_load_lds(src + int64_t(i0) * NC + (d - NC * v0), EPK_LDS(dst + (d - lane)), 4, 0, 0);
+    __builtin_amdgcn_global_load_lds(src + int64_t(i1) * NC + (d + nt - NC * v1), EPK_LDS(dst + (d + nt - lane)), 4,
                                      0, 0);
+  }
+  if (d < nd) {
+    const int v0 = d / NC;
+    __builtin_amdgcn_global_load_lds(src + int64_t(ids[v0]) * NC + (d - NC * v0), EPK_LDS(dst + (d - lane)), 4, 0, 0);
+  }
 }
 
 __device__ __forceinline__ void wait_staged() {
   __builtin_amdgcn_s_waitcnt(0);  // all direct-to-LDS loads of this wave have landed
   __syncthreads();
 }
+
+// Workgroup barrier for LDS traffic: waits for this wave's LDS accesses only.
+// A __syncthreads() would also wait for every direct-to-LDS load still in
+// flight, which the pipelined kernels issue for the next part on purpose.
+// The memory clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 struct PartHdr {
   int e0, ne, own0, nown, f0, nf, lofs, U;
@@ -162,56 +168,67 @@ __device__ __forceinline__ void dma_incidence(uint16_t *inc, uint16_t *lo, const
             tid, nt);
 }
 
+// Edge index of lane j of a part, clamped into [e0, e0 + ne) and, for an
+// empty part, into the edge array: lanes past the last edge re-read an edge
+// they never use, so every lane issues the same loads and no branch (and no
+// wait for the header) separates them.
+__device__ __forceinline__ int64_t clamp_edge(const DevPlan &P, int e0, int ne, int j) {
+  return min(int64_t(e0) + max(min(j, ne - 1), 0), P.m - 1);
+}
+
+// Edge endpoints and geometry into registers.
 template <int G, int EPT>
 __device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, int tid, int nt, uint32_t ew[EPT],
                                            float4 eg[EPT]) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
-    const int j = tid + k * nt;
-    ew[k] = 0u;
-    eg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (j < h.ne) {
-      ew[k] = P.eloc[h.e0 + j];
-      load_geom<G>(P.geom, int64_t(h.e0) + j, eg[k].x, eg[k].y, eg[k].z, eg[k].w);
-    }
+    const int64_t e = clamp_edge(P, h.e0, h.ne, tid + k * nt);
+    ew[k] = P.eloc[e];
+    eg[k] = load_geom<G>(P.geom, e);
   }
 }
 
 // ------------------------------------------------------------------ FLUX5 parts
+//
+// A part goes through three dependent loads and a compute stage:
+//   H  its header (8 dwords);
+//   A  its foreign ids into an LDS id buffer (addresses from H);
+//   B  owned rows and foreign rows (by id) into an LDS state buffer, the local
+//      incidence lists and offsets into LDS, edge data into registers;
+//   C  flux from LDS, per-vertex sums in a fixed order, the writes.
+// The direct kernels run one part per workgroup and wait after each load
+// stage.  The pipelined kernels run a fixed grid that overlaps the stages of
+// consecutive parts of one workgroup (see flux_*_pipe).
 
-// LDS: st[max_u][5] | (QNEW: acc[max_u][5]) | flx[cap][5] | inc[2 cap] u16 | lo[max_u + 2] u16.
-// Without q_new the per-vertex sums overwrite st (no thread reads st then).
-template <int G, bool QNEW, int EPT>
-__device__ __forceinline__ void flux_fwd_part(const DevPlan &P, int part, const float *__restrict__ q,
-                                              float *__restrict__ r, float *__restrict__ qn, float dt,
-                                              float *__restrict__ ws, float *smem) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const PartHdr h = load_hdr(P, part);
-  float *st = smem;
-  float *acc = QNEW ? st + P.max_u * 5 : st;
-  float *flx = (QNEW ? acc : st) + P.max_u * 5;
-  uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
-  uint16_t *lo = inc + 2 * P.cap;
+__device__ __forceinline__ void stage_ids(const DevPlan &P, const PartHdr &h, int32_t *ids, int tid, int nt) {
+  dma_block(reinterpret_cast<float *>(ids), reinterpret_cast<const float *>(P.fid + h.f0), h.nf, tid, nt);
+}
 
-  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  dma_incidence(inc, lo, P, h, tid, nt);
-  uint32_t ew[EPT];
-  float4 eg[EPT];
-  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
-  dma_foreign(st + h.nown * 5, q, P.fid + h.f0, h.nf, tid, nt);
-  wait_staged();
+// Rows of one [n][5] state array for a part: owned block, then foreign rows.
+__device__ __forceinline__ void stage_state(const PartHdr &h, const float *__restrict__ src, float *dst,
+                                            const int32_t *ids, int tid, int nt) {
+  dma_block(dst, src + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_rows<5>(dst + h.nown * 5, src, ids, h.nf, tid, nt);
+}
 
+// Forward compute stage.  st holds the part's states; the per-vertex sums go
+// to acc (acc may be st when q_new is not written); flx: cap * 5 floats.
+template <int G, int EPT>
+__device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, float *acc, float *flx,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int j = tid + k * nt;
     if (j < h.ne) {
       float F[5];
-      edge_flux(st + (ew[k] & 0xffffu) * 5, st + (ew[k] >> 16) * 5, eg[k].x, eg[k].y, eg[k].z, eg[k].w, F);
+      edge_flux(st + (ew[k] & 0xffffu) * 5, st + (ew[k] >> 16) * 5, eg[k].x, eg[k].y, eg[k].z, geom_area<G>(eg[k]),
+                F);
 #pragma unroll
       for (int c = 0; c < 5; ++c) flx[j * 5 + c] = F[c];
     }
   }
-  __syncthreads();
+  lds_sync();
 
   for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -230,8 +247,14 @@ __device__ __forceinline__ void flux_fwd_part(const DevPlan &P, int part, const 
 #pragma unroll
     for (int c = 0; c < 5; ++c) acc[i * 5 + c] = s[c];
   }
-  __syncthreads();
+  lds_sync();
+}
 
+// Forward writes of a computed part: owned sums (and q_new) to the output,
+// foreign sums to the part's workspace slots.
+template <bool QNEW>
+__device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, const float *acc, float *__restrict__ r,
+                                          float *__restrict__ qn, float dt, float *__restrict__ ws, int tid, int nt) {
   float *ro = r + int64_t(h.own0) * 5;
   for (int d = tid; d < h.nown * 5; d += nt) {
     ro[d] = acc[d];
@@ -241,37 +264,19 @@ __device__ __forceinline__ void flux_fwd_part(const DevPlan &P, int part, const 
   for (int d = tid; d < h.nf * 5; d += nt) wo[d] = acc[h.nown * 5 + d];
 }
 
-// LDS: st[max_u][5] | gs[max_u][5] (then the per-vertex sums) | vu[cap][5] | vv[cap][5] | inc | lo.
+// Adjoint compute stage.  st: states, gs: upstream gradients (overwritten by
+// the per-vertex sums); vu, vv: cap * 5 floats each.
 template <int G, int EPT>
-__device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const float *__restrict__ q,
-                                              const float *__restrict__ gr, float *__restrict__ gq,
-                                              float *__restrict__ ws, float *smem) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const PartHdr h = load_hdr(P, part);
-  float *st = smem;
-  float *gs = st + P.max_u * 5;
-  float *vu = gs + P.max_u * 5;
-  float *vv = vu + P.cap * 5;
-  uint16_t *inc = reinterpret_cast<uint16_t *>(vv + P.cap * 5);
-  uint16_t *lo = inc + 2 * P.cap;
-
-  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  dma_block(gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  dma_incidence(inc, lo, P, h, tid, nt);
-  uint32_t ew[EPT];
-  float4 eg[EPT];
-  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
-  dma_foreign(st + h.nown * 5, q, P.fid + h.f0, h.nf, tid, nt);
-  dma_foreign(gs + h.nown * 5, gr, P.fid + h.f0, h.nf, tid, nt);
-  wait_staged();
-
+__device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, float *gs, float *vu, float *vv,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int j = tid + k * nt;
     if (j < h.ne) {
       const int lu = ew[k] & 0xffffu, lv = ew[k] >> 16;
       // d(a F)/dq = a J(q, n) / 2 +- a sigma I / 2 = J(q, A) / 2 +- a sigma I / 2 (J linear in n)
-      const float hs = 0.5f * kSigma * eg[k].w;
+      const float hs = 0.5f * kSigma * geom_area<G>(eg[k]);
       float d[5], ju[5], jv[5];
 #pragma unroll
       for (int c = 0; c < 5; ++c) d[c] = gs[lu * 5 + c] - gs[lv * 5 + c];
@@ -284,7 +289,7 @@ __device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const 
       }
     }
   }
-  __syncthreads();
+  lds_sync();
 
   for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -298,14 +303,21 @@ __device__ __forceinline__ void flux_bwd_part(const DevPlan &P, int part, const 
 #pragma unroll
     for (int c = 0; c < 5; ++c) gs[i * 5 + c] = s[c];
   }
-  __syncthreads();
+  lds_sync();
+}
 
+__device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, float *__restrict__ gq,
+                                          float *__restrict__ ws, int tid, int nt) {
   float *go = gq + int64_t(h.own0) * 5;
   for (int d = tid; d < h.nown * 5; d += nt) go[d] = gs[d];
   float *wo = ws + int64_t(h.f0) * 5;
   for (int d = tid; d < h.nf * 5; d += nt) wo[d] = gs[h.nown * 5 + d];
 }
 
+// ---- direct kernels: one part per workgroup
+
+// LDS: st[max_u][5] | (QNEW: acc[max_u][5]) | flx[cap][5] (the ids until the
+// flux stage) | inc[2 cap] u16 | lo[max_u + 2] u16.
 template <int G, bool QNEW, int EPT>
 __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
                                                         float *__restrict__ qn, float dt, float *__restrict__ ws,
@@ -313,9 +325,29 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
-  flux_fwd_part<G, QNEW, EPT>(P, part, q, r, qn, dt, ws, smem);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  float *st = smem;
+  float *acc = QNEW ? st + P.max_u * 5 : st;
+  float *flx = (QNEW ? acc : st) + P.max_u * 5;
+  uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
+  uint16_t *lo = inc + 2 * P.cap;
+  int32_t *ids = reinterpret_cast<int32_t *>(flx);
+  const PartHdr h = load_hdr(P, part);
+  stage_ids(P, h, ids, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  wait_staged();
+  dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
+  wait_staged();
+  compute_fwd<G, EPT>(h, st, acc, flx, inc, lo, ew, eg, tid, nt);
+  write_fwd<QNEW>(h, st, acc, r, qn, dt, ws, tid, nt);
 }
 
+// LDS: st[max_u][5] | gs[max_u][5] | vu[cap][5] (the ids until the flux
+// stage) | vv[cap][5] | inc | lo.
 template <int G, int EPT>
 __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *__restrict__ q,
                                                         const float *__restrict__ gr, float *__restrict__ gq,
@@ -323,59 +355,218 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
-  flux_bwd_part<G, EPT>(P, part, q, gr, gq, ws, smem);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  float *st = smem;
+  float *gs = st + P.max_u * 5;
+  float *vu = gs + P.max_u * 5;
+  float *vv = vu + P.cap * 5;
+  uint16_t *inc = reinterpret_cast<uint16_t *>(vv + P.cap * 5);
+  uint16_t *lo = inc + 2 * P.cap;
+  int32_t *ids = reinterpret_cast<int32_t *>(vu);
+  const PartHdr h = load_hdr(P, part);
+  stage_ids(P, h, ids, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_block(gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  wait_staged();
+  dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
+  dma_rows<5>(gs + h.nown * 5, gr, ids, h.nf, tid, nt);
+  wait_staged();
+  compute_bwd<G, EPT>(h, st, gs, vu, vv, inc, lo, ew, eg, tid, nt);
+  write_bwd(h, gs, gq, ws, tid, nt);
 }
 
-// Persistent variant: a fixed grid takes parts from a queue (largest first).
-// Every workgroup stops after drawing one ticket past the last item; the
-// workgroup that stops last resets both counters, so the next launch (and
-// every replay of a captured graph) starts from zero.
-__device__ __forceinline__ int next_item(const DevPlan &P, int *s_item) {
-  if (threadIdx.x == 0) {
-    const uint32_t t = atomicAdd(&P.queue[0], 1u);
-    int item = -1;
-    if (t < uint32_t(P.k)) {
-      item = P.items[t];
-    } else {
-      const uint32_t done = atomicAdd(&P.queue[1], 1u);
-      if (done == uint32_t(P.grid) - 1u) {
-        atomicExch(&P.queue[0], 0u);
-        atomicExch(&P.queue[1], 0u);
-      }
+// ---- pipelined persistent kernels
+//
+// Workgroup b walks its own list of parts, t = 0, 1, ...  Iteration t waits
+// once for every load issued before it, then issues B(t+1), A(t+2) and H(t+3)
+// and computes C(t), so the loads of three parts overlap the compute of a
+// fourth.  LDS holds two id buffers, two state buffers and two incidence
+// buffers; a buffer is reloaded only after the barrier that follows its last
+// reader.  A header of a part past the end of the list is all zero, which
+// makes its stages empty (edge loads read edge 0 and are never used).
+//
+// Part lists.  swizzle = 1: workgroup b runs on XCD b mod 8 and takes the
+// parts x*chunk + b/8 + t*(grid/8) of that XCD's range (grid a multiple of 8),
+// so the workgroups of one XCD work on neighbouring parts at the same time.
+// swizzle = 0: part b + t*grid (a batch image stores its headers in
+// processing order, largest parts first).
+
+__device__ __forceinline__ int pipe_part(int k, int t, int swizzle) {
+  const int b = blockIdx.x, G = gridDim.x;
+  if (swizzle) {
+    const int chunk = (k + 7) >> 3;
+    const int i = (b >> 3) + t * (G >> 3);
+    const int part = (b & 7) * chunk + i;
+    return (i < chunk && part < k) ? part : -1;
+  }
+  const int part = b + t * G;
+  return part < k ? part : -1;
+}
+
+// Header of a part as one dword per lane (lane l holds field l mod 8); zero
+// for a part past the end.  Read into scalars only after the loop's wait.
+__device__ __forceinline__ int hdr_lanes(const DevPlan &P, int part) {
+  if (part < 0) return 0;
+  return P.hdr[int64_t(part) * kHdrInts + (threadIdx.x & 7)];
+}
+
+__device__ __forceinline__ PartHdr hdr_unpack(int v) {
+  return {__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1), __builtin_amdgcn_readlane(v, 2),
+          __builtin_amdgcn_readlane(v, 3), __builtin_amdgcn_readlane(v, 4), __builtin_amdgcn_readlane(v, 5),
+          __builtin_amdgcn_readlane(v, 6), __builtin_amdgcn_readlane(v, 7)};
+}
+
+// LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):
+// st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | (q_new: acc[max_u][5]) |
+// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
+// lo[2][nlo] u16.  Buffers are addressed by arithmetic on the one LDS base,
+// so every pointer stays an LDS pointer (no indexed pointer arrays).
+struct PipeLds {
+  float *base;
+  int su, sf, nf, cap, nlo, o_gs, o_acc, o_f0, o_f1, o_ids;
+  __device__ float *st(int b) const { return base + b * su; }
+  __device__ float *gs(int b) const { return base + o_gs + b * su; }
+  __device__ float *acc() const { return base + o_acc; }
+  __device__ float *f0() const { return base + o_f0; }
+  __device__ float *f1() const { return base + o_f1; }
+  __device__ int32_t *ids(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + b * nf; }
+  __device__ uint16_t *inc(int b) const {
+    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + b * (2 * cap);
+  }
+  __device__ uint16_t *lo(int b) const {
+    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + 4 * cap + b * nlo;
+  }
+};
+
+__device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd, bool qnew) {
+  PipeLds L;
+  L.base = smem;
+  L.su = P.max_u * 5;
+  L.sf = P.cap * 5;
+  L.nf = P.max_nf;
+  L.cap = P.cap;
+  L.nlo = (P.max_u + 3) & ~1;  // U + 1 offsets, read as whole dwords
+  int o = 2 * L.su;
+  L.o_gs = o;
+  o += bwd ? 2 * L.su : 0;
+  L.o_acc = o;
+  o += qnew ? L.su : 0;
+  L.o_f0 = o;
+  o += L.sf;
+  L.o_f1 = o;
+  o += bwd ? L.sf : 0;
+  L.o_ids = o;
+  return L;
+}
+
+template <int G, bool QNEW, int EPT>
+__global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
+                                                     float *__restrict__ qn, float dt, float *__restrict__ ws,
+                                                     int swizzle) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const PipeLds L = pipe_lds(P, smem, false, QNEW);
+  uint32_t ew[EPT], ewn[EPT];
+  float4 eg[EPT], egn[EPT];
+
+  // prologue: H(0); A(0), H(1); B(0), A(1), H(2)
+  int hv = hdr_lanes(P, pipe_part(P.k, 0, swizzle));
+  wait_staged();
+  PartHdr h0 = hdr_unpack(hv);
+  hv = hdr_lanes(P, pipe_part(P.k, 1, swizzle));
+  stage_ids(P, h0, L.ids(0), tid, nt);
+  wait_staged();
+  PartHdr h1 = hdr_unpack(hv);
+  hv = hdr_lanes(P, pipe_part(P.k, 2, swizzle));
+  stage_ids(P, h1, L.ids(1), tid, nt);
+  stage_state(h0, q, L.st(0), L.ids(0), tid, nt);
+  dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
+  load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
+
+  // The writes of part t-1 open iteration t: issued right after the wait,
+  // they complete while part t is computed instead of delaying the next wait.
+  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};  // part t-1 (none yet: writes nothing)
+  int t = 0;
+  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+    const int b = t & 1, nb = b ^ 1;
+    wait_staged();
+    const PartHdr h2 = hdr_unpack(hv);
+    write_fwd<QNEW>(hp, L.st(nb), QNEW ? L.acc() : L.st(nb), r, qn, dt, ws, tid, nt);  // W(t-1)
+    lds_sync();                                           // buffer nb and acc are free again
+    hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));   // H(t+3)
+    stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);     // B(t+1)
+    dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
+    load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
+    stage_ids(P, h2, L.ids(b), tid, nt);                  // A(t+2)
+    compute_fwd<G, EPT>(h0, L.st(b), QNEW ? L.acc() : L.st(b), L.f0(), L.inc(b), L.lo(b), ew, eg, tid, nt);  // C(t)
+    hp = h0;
+    h0 = h1;
+    h1 = h2;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      ew[k] = ewn[k];
+      eg[k] = egn[k];
     }
-    *s_item = item;
   }
-  __syncthreads();
-  const int item = *s_item;
-  __syncthreads();
-  return item;
+  const int pb = (t + 1) & 1;  // buffer of part t-1
+  write_fwd<QNEW>(hp, L.st(pb), QNEW ? L.acc() : L.st(pb), r, qn, dt, ws, tid, nt);
+  __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
 }
 
-template <int EPT>
-__global__ void __launch_bounds__(256) flux_fwd_persistent(DevPlan P, const float *__restrict__ q,
-                                                            float *__restrict__ r, float *__restrict__ ws) {
+template <int G, int EPT>
+__global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__restrict__ q,
+                                                     const float *__restrict__ gr, float *__restrict__ gq,
+                                                     float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
-  __shared__ int s_item;
-  for (;;) {
-    const int part = next_item(P, &s_item);
-    if (part < 0) break;
-    flux_fwd_part<4, false, EPT>(P, part, q, r, nullptr, 0.f, ws, smem);
-    __syncthreads();
-  }
-}
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const PipeLds L = pipe_lds(P, smem, true, false);
+  uint32_t ew[EPT], ewn[EPT];
+  float4 eg[EPT], egn[EPT];
 
-template <int EPT>
-__global__ void __launch_bounds__(256) flux_bwd_persistent(DevPlan P, const float *__restrict__ q,
-                                                            const float *__restrict__ gr, float *__restrict__ gq,
-                                                            float *__restrict__ ws) {
-  extern __shared__ float smem[];
-  __shared__ int s_item;
-  for (;;) {
-    const int part = next_item(P, &s_item);
-    if (part < 0) break;
-    flux_bwd_part<4, EPT>(P, part, q, gr, gq, ws, smem);
-    __syncthreads();
+  int hv = hdr_lanes(P, pipe_part(P.k, 0, swizzle));
+  wait_staged();
+  PartHdr h0 = hdr_unpack(hv);
+  hv = hdr_lanes(P, pipe_part(P.k, 1, swizzle));
+  stage_ids(P, h0, L.ids(0), tid, nt);
+  wait_staged();
+  PartHdr h1 = hdr_unpack(hv);
+  hv = hdr_lanes(P, pipe_part(P.k, 2, swizzle));
+  stage_ids(P, h1, L.ids(1), tid, nt);
+  stage_state(h0, q, L.st(0), L.ids(0), tid, nt);
+  stage_state(h0, gr, L.gs(0), L.ids(0), tid, nt);
+  dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
+  load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
+
+  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};
+  int t = 0;
+  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+    const int b = t & 1, nb = b ^ 1;
+    wait_staged();
+    const PartHdr h2 = hdr_unpack(hv);
+    write_bwd(hp, L.gs(nb), gq, ws, tid, nt);
+    lds_sync();
+    hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));
+    stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);
+    stage_state(h1, gr, L.gs(nb), L.ids(nb), tid, nt);
+    dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
+    load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
+    stage_ids(P, h2, L.ids(b), tid, nt);
+    compute_bwd<G, EPT>(h0, L.st(b), L.gs(b), L.f0(), L.f1(), L.inc(b), L.lo(b), ew, eg, tid, nt);
+    hp = h0;
+    h0 = h1;
+    h1 = h2;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      ew[k] = ewn[k];
+      eg[k] = egn[k];
+    }
   }
+  write_bwd(hp, L.gs((t + 1) & 1), gq, ws, tid, nt);
+  __builtin_amdgcn_s_waitcnt(0);
 }
 
 // ------------------------------------------------------------------ SpMV
@@ -398,26 +589,19 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   float *tval = reinterpret_cast<float *>(tkey + (nt >> 6));
   const int lane = tid & 63, wave = tid >> 6;
 
-  // owned x block straight to LDS; edge data and foreign x ids in one batch of loads
+  // batch 1: owned x block, foreign x ids (into the slots their values will
+  // take) and edge data; batch 2: foreign x values, each lane overwriting the id
+  // it read
+  int32_t *xid = reinterpret_cast<int32_t *>(xs + xn);
   dma_block(xs, x + xo, xn, tid, nt);
+  dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.fid + xf0), xnf, tid, nt);
   const bool valid = tid < ne;
-  const uint32_t w = valid ? P.eloc[e0 + tid] : 0u;
-  const float wt = valid ? P.geom[e0 + tid] : 0.0f;
-  const uint32_t w_next = (lane == 63 && tid + 1 < ne) ? P.eloc[e0 + tid + 1] : 0u;
-  const int32_t *fids = P.fid + xf0;
-  int fr[kMaxFI];
-#pragma unroll
-  for (int k = 0; k < kMaxFI; ++k) {
-    const int d = tid + k * nt;
-    fr[k] = d < xnf ? fids[d] : 0;
-  }
-#pragma unroll
-  for (int k = 0; k < kMaxFI; ++k) {
-    const int d = tid + k * nt;
-    if (d < xnf) __builtin_amdgcn_global_load_lds(x + fr[k], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
-  }
-  for (int d = tid + kMaxFI * nt; d < xnf; d += nt)
-    __builtin_amdgcn_global_load_lds(x + fids[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
+  const int64_t ec = clamp_edge(P, int(e0), ne, tid);
+  const uint32_t w = P.eloc[ec];
+  const float wt = P.geom[ec];
+  const uint32_t w_next = P.eloc[clamp_edge(P, int(e0), ne, tid + 1)];
+  wait_staged();
+  for (int d = tid; d < xnf; d += nt) __builtin_amdgcn_global_load_lds(x + xid[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
   wait_staged();
 
   // one edge per thread, edges sorted by local y: inclusive segmented scan per wavefront
@@ -598,17 +782,37 @@ hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q,
   return hipGetLastError();
 }
 
-hipError_t launch_flux_persistent(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
-                                  float *ws, bool backward, hipStream_t s) {
-  if (P.k == 0) return hipSuccess;
-  const dim3 grid(P.grid), block(wg);
-  const int ept = edges_per_thread(P.cap, wg);
-  if (backward) {
-    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_persistent<E>), grid, block, lds, s, P, q, gr, out, ws))
-  } else {
-    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_persistent<E>), grid, block, lds, s, P, q, out, ws))
+// The pipelined kernel instance for (adjoint?, geometry width, q_new?, edges per thread).
+static const void *pipe_fn(bool bwd, int G, bool qnew, int ept) {
+#define EPK_PIPE_FN(E)                                                                                        \
+  if (ept == E) {                                                                                              \
+    if (bwd) return G == 4 ? reinterpret_cast<const void *>(&flux_bwd_pipe<4, E>)                             \
+                           : reinterpret_cast<const void *>(&flux_bwd_pipe<2, E>);                            \
+    if (G == 4) return qnew ? reinterpret_cast<const void *>(&flux_fwd_pipe<4, true, E>)                       \
+                            : reinterpret_cast<const void *>(&flux_fwd_pipe<4, false, E>);                     \
+    return qnew ? reinterpret_cast<const void *>(&flux_fwd_pipe<2, true, E>)                                   \
+                : reinterpret_cast<const void *>(&flux_fwd_pipe<2, false, E>);                                 \
   }
-  return hipGetLastError();
+  EPK_PIPE_FN(1)
+  EPK_PIPE_FN(2)
+  EPK_PIPE_FN(4)
+  EPK_PIPE_FN(8)
+#undef EPK_PIPE_FN
+  return nullptr;
+}
+
+hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, const float *q, const float *gr,
+                            float *out, float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s) {
+  if (P.k == 0) return hipSuccess;
+  const void *fn = pipe_fn(backward, P.geom_ncomp, qn != nullptr, edges_per_thread(P.cap, wg));
+  if (!fn || grid < 1 || (swizzle && grid % 8)) return hipErrorInvalidValue;
+  DevPlan Pa = P;
+  if (backward) {
+    void *args[] = {&Pa, &q, &gr, &out, &ws, &swizzle};
+    return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, lds, s);
+  }
+  void *args[] = {&Pa, &q, &out, &qn, &dt, &ws, &swizzle};
+  return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, lds, s);
 }
 
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
@@ -645,23 +849,10 @@ hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int6
   return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int wg, size_t lds, bool backward, int cap) {
+int pipe_blocks_per_cu(int wg, size_t lds, bool backward, int G, bool qnew, int cap) {
+  const void *fn = pipe_fn(backward, G, qnew, edges_per_thread(cap, wg));
   int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
-  const int ept = edges_per_thread(cap, wg);
-  const void *fn = nullptr;
-  if (backward)
-    fn = ept == 1 ? reinterpret_cast<const void *>(&flux_bwd_persistent<1>)
-       : ept == 2 ? reinterpret_cast<const void *>(&flux_bwd_persistent<2>)
-       : ept == 4 ? reinterpret_cast<const void *>(&flux_bwd_persistent<4>)
-                  : reinterpret_cast<const void *>(&flux_bwd_persistent<8>);
-  else
-    fn = ept == 1 ? reinterpret_cast<const void *>(&flux_fwd_persistent<1>)
-       : ept == 2 ? reinterpret_cast<const void *>(&flux_fwd_persistent<2>)
-       : ept == 4 ? reinterpret_cast<const void *>(&flux_fwd_persistent<4>)
-                  : reinterpret_cast<const void *>(&flux_fwd_persistent<8>);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, lds);
-  if (e != hipSuccess || nb < 1) return 1;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, lds) != hipSuccess || nb < 1) return 1;
   return nb;
 }
 

@@ -39,6 +39,15 @@ int64_t flux_bwd_lds(int64_t max_u, int64_t cap) {
   const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + max_u + 2);
   return (b + 15) & ~int64_t(15);
 }
+// Mirror of the device carve-up of the pipelined kernels: two state buffers
+// (two more for the adjoint's gradients), q_new sums, one (two) edge value
+// buffer(s), two id buffers, two incidence lists and two offset lists.
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew) {
+  const int64_t su = 5 * max_u, sf = 5 * cap, nlo = (max_u + 3) & ~int64_t(1);
+  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
+                    2 * (4 * cap + 2 * nlo);
+  return (b + 15) & ~int64_t(15);
+}
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
   const int64_t b = 4 * (max_ux + max_uy) + 8 * (wg / 64);
   return (b + 15) & ~int64_t(15);
@@ -175,7 +184,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::vector<int32_t> fid;  // device foreign-id list (FLUX5: all; SpMV: x only)
     fid.reserve(size_t(P->stats.cost));
     std::vector<int32_t> red_foreign;  // packed ids of the reduced class's foreign entries, part-major
-    int64_t max_u[2] = {0, 0};
+    int64_t max_u[2] = {0, 0}, max_nf = 0;
     std::vector<int32_t> fl[2];
     std::vector<int32_t> cnt, cur;
     std::vector<int64_t> order_idx;
@@ -214,6 +223,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
           return nullptr;
         }
         max_u[c] = std::max(max_u[c], U);
+        max_nf = std::max<int64_t>(max_nf, nf[c]);
       }
       auto local = [&](int32_t w) -> uint32_t {
         const int c = cls(w);
@@ -292,6 +302,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     }
     P->max_u = max_u[0];
     P->max_uy = max_u[1];
+    P->max_nf = max_nf;
 
     // ---- reduction tables: for each replicated vertex of the reduced class,
     // its slots (non-owner parts) in ascending part order.
@@ -361,6 +372,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->lds_fwd = flux_fwd_lds(P->max_u, cap, false);
       P->lds_fwd_qn = flux_fwd_lds(P->max_u, cap, true);
       P->lds_bwd = flux_bwd_lds(P->max_u, cap);
+      P->lds_pipe_fwd = flux_pipe_lds(P->max_u, P->max_nf, cap, false, false);
+      P->lds_pipe_fwd_qn = flux_pipe_lds(P->max_u, P->max_nf, cap, false, true);
+      P->lds_pipe_bwd = flux_pipe_lds(P->max_u, P->max_nf, cap, true, false);
       const int64_t G = gstore, na = P->n_active_out;
       const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
@@ -459,16 +473,21 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s) {
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
   epk::clear_error();
   if (!p || !info) return epk::fail(EPK_EINVAL, "NULL argument");
-  const int64_t v[9] = {p->k,
-                        p->lds_fwd,
-                        p->lds_bwd,
-                        p->wg,
-                        p->ncls,
-                        p->bytes_fwd_kernel + p->bytes_reduce,
-                        p->bytes_bwd_kernel + p->bytes_reduce,
-                        p->bytes_fwd_kernel,
-                        p->bytes_bwd_kernel};
-  for (int32_t i = 0; i < n_info && i < 9; ++i) info[i] = v[i];
+  const int64_t v[14] = {p->k,
+                         p->lds_fwd,
+                         p->lds_bwd,
+                         p->wg,
+                         p->ncls,
+                         p->bytes_fwd_kernel + p->bytes_reduce,
+                         p->bytes_bwd_kernel + p->bytes_reduce,
+                         p->bytes_fwd_kernel,
+                         p->bytes_bwd_kernel,
+                         p->max_nf,
+                         p->pipe,
+                         p->pipe ? p->grid_pipe_fwd : 0,
+                         p->pipe ? p->grid_pipe_bwd : 0,
+                         p->lds_pipe_bwd};
+  for (int32_t i = 0; i < n_info && i < 14; ++i) info[i] = v[i];
   return EPK_OK;
 }
 
@@ -486,6 +505,7 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
     if (p->kind == EPK_SPMV) p->lds_fwd = p->lds_bwd = epk::spmv_lds(p->max_u, p->max_uy, wg);
   }
   if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
+  p->pipe = 0;  // the pipelined grid depends on both: set it again
   return EPK_OK;
 }
 
