@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-GRAPH_TIMING = False  # set by --graph
+GRAPH_TIMING = True  # cleared by --eager
 COLD_STEPS = 10  # set by --cold-steps
 CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
 
@@ -65,10 +65,10 @@ def _args():
     ap.add_argument("--cap", type=int, default=256)
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
-    ap.add_argument("--pipe", type=int, default=-1,
+    ap.add_argument("--pipe", type=int, default=0,
                     help="pipelined persistent launch, workgroups per CU (-1: as many as fit, 0: one per part)")
-    ap.add_argument("--graph", action="store_true",
-                    help="time the K steps as one captured HIP graph (timing events inside the graph)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time K eagerly launched steps instead of one HIP graph holding the K steps")
     ap.add_argument("--cold-steps", type=int, default=10,
                     help="extra steps timed after a 1 GiB cache scrub each (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -289,7 +289,7 @@ def cpu_baseline_spmv(R, budget_s):
 def main():
     args = _args()
     global GRAPH_TIMING, COLD_STEPS
-    GRAPH_TIMING = args.graph
+    GRAPH_TIMING = not args.eager
     COLD_STEPS = args.cold_steps
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -353,7 +353,7 @@ def main():
                         f"(loss sum r^2), partitioned (EP) task order",
             "capacity": args.cap,
             "order": "ep",
-            "timing": "hip-graph replay of the timed steps" if args.graph else "eager launches",
+            "timing": "eager launches" if args.eager else "hip-graph replay of the timed steps",
             "launch": (f"pipelined persistent, grid {ep['info']['grid_pipe_fwd']} fwd / {ep['info']['grid_pipe_bwd']} bwd"
                        if ep["info"]["pipe"] else "one workgroup per part"),
         },

@@ -149,6 +149,8 @@ __device__ __forceinline__ void wait_staged() {
 // The memory clobber keeps the compiler from moving memory accesses across it.
 __device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+constexpr int kIncBatch = 4;  // incidence entries per vertex read as one batch (mesh degrees are <= 4)
+
 struct PartHdr {
   int e0, ne, own0, nown, f0, nf, lofs, U;
 };
@@ -232,17 +234,31 @@ __device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, f
 
   for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int t1 = lo[i + 1];
-    for (int t = lo[i]; t < t1; ++t) {
-      const int x = inc[t];
-      const float *f = flx + (x >> 1) * 5;
-      if (x & 1) {
+    const int t0 = lo[i], t1 = lo[i + 1];
+    // the first kIncBatch entries: their indices, then their rows, each as one
+    // batch of LDS reads; the sum still runs in list order
+    int x[kIncBatch];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) s[c] -= f[c];
-      } else {
+    for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
+    float v[kIncBatch][5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) s[c] += f[c];
-      }
+    for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
+      const float *f = flx + (max(x[k], 0) >> 1) * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[k][c] = f[c];
+    }
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) {
+      const float sg = x[k] < 0 ? 0.f : (x[k] & 1) ? -1.f : 1.f;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) s[c] += sg * (x[k] < 0 ? 0.f : v[k][c]);
+    }
+    for (int t = t0 + kIncBatch; t < t1; ++t) {
+      const int y = inc[t];
+      const float *f = flx + (y >> 1) * 5;
+      const float sg = (y & 1) ? -1.f : 1.f;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) s[c] += sg * f[c];
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) acc[i * 5 + c] = s[c];
@@ -293,10 +309,26 @@ __device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, f
 
   for (int i = tid; i < h.U; i += nt) {
     float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int t1 = lo[i + 1];
-    for (int t = lo[i]; t < t1; ++t) {
-      const int x = inc[t];
-      const float *f = ((x & 1) ? vv : vu) + (x >> 1) * 5;
+    const int t0 = lo[i], t1 = lo[i + 1];
+    int x[kIncBatch];
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
+    float v[kIncBatch][5];
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
+      const int y = max(x[k], 0);
+      const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[k][c] = f[c];
+    }
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) s[c] += x[k] < 0 ? 0.f : v[k][c];
+    }
+    for (int t = t0 + kIncBatch; t < t1; ++t) {
+      const int y = inc[t];
+      const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
 #pragma unroll
       for (int c = 0; c < 5; ++c) s[c] += f[c];
     }
