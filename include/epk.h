@@ -137,7 +137,8 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s);
  * [7] = forward-kernel-only bytes, [8] = adjoint-kernel-only bytes,
  * [9] = max foreign vertices of a part, [10] = pipelined launch setting
  * (0: off), [11] / [12] = its forward / adjoint grid, [13] = its adjoint
- * LDS bytes.                                                              */
+ * LDS bytes, [14] = workspace layout in use (0 part-major, 1 vertex-major).
+ * The byte counts follow the layout in use.                               */
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
  * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
@@ -156,6 +157,16 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle);
  * epk_plan_set_launch switches it off again.  EPK_ERANGE if the double
  * buffers do not fit in a workgroup's LDS.                                */
 int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
+/* Layout of the replicated vertices' partials in the workspace (d_ws):
+ * 0 part-major (each part writes its foreign partials as one block and the
+ * reduction gathers a vertex's partials through a slot list), 1 vertex-major
+ * (each part scatters its partials so that a vertex's partials sit side by
+ * side and the reduction reads them as one run), -1 automatic (vertex-major
+ * when the reduced class has more than four partials per replicated vertex,
+ * as around power-law hubs).  The sum order, ascending part id, and hence
+ * every result bit, is the same under both.  Host only; takes effect at the
+ * next launch.                                                            */
+int epk_plan_set_slot_layout(epk_plan *p, int32_t layout);
 void epk_plan_destroy(epk_plan *p);
 
 /* ---------------------------------------------------------------- device */

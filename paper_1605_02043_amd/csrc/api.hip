@@ -35,7 +35,8 @@ DevPlan dev_plan(const epk_plan *p) {
   P.fid = dptr<int32_t>(b, L.fid);
   P.rvid = dptr<int32_t>(b, L.rvid);
   P.roff = dptr<int32_t>(b, L.roff);
-  P.rslot = dptr<int32_t>(b, L.rslot);
+  P.sidx = p->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;
+  P.rslot = p->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = nullptr;
   P.m = p->m;
@@ -66,7 +67,8 @@ DevPlan dev_batch(const epk_batch *bt) {
   P.fid = dptr<int32_t>(b, L.fid);
   P.rvid = dptr<int32_t>(b, L.rvid);
   P.roff = dptr<int32_t>(b, L.roff);
-  P.rslot = dptr<int32_t>(b, L.rslot);
+  P.sidx = bt->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;
+  P.rslot = bt->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = dptr<int32_t>(b, L.iso);
   P.m = bt->m;
@@ -116,7 +118,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   epk_batch *B = new epk_batch();
   B->n_graphs = n_graphs;
   B->voff.assign(size_t(n_graphs) + 1, 0);
-  std::vector<int32_t> hdr, fid, rvid, roff(1, 0), rslot, heavy, iso;
+  std::vector<int32_t> hdr, fid, rvid, roff(1, 0), sidx, rslot, heavy, iso;
   std::vector<uint32_t> eloc;
   std::vector<float> geom;
   std::vector<uint16_t> inc, loff;
@@ -148,15 +150,19 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
       rvid.push_back(int32_t(hptr<int32_t>(p, L.rvid)[i] + voff));
       roff.push_back(int32_t(hptr<int32_t>(p, L.roff)[i + 1] + foff));
     }
-    for (int64_t i = 0; i < C; ++i) rslot.push_back(int32_t(hptr<int32_t>(p, L.rslot)[i] + foff));
+    for (int64_t i = 0; i < C; ++i) {
+      sidx.push_back(int32_t(hptr<int32_t>(p, L.sidx)[i] + foff));
+      rslot.push_back(int32_t(hptr<int32_t>(p, L.rslot)[i] + foff));
+    }
     for (int64_t i = 0; i < p->n_heavy; ++i) heavy.push_back(int32_t(hptr<int32_t>(p, L.heavy)[i] + rbase));
     for (int64_t v = p->n_active_out; v < p->n_out; ++v) iso.push_back(int32_t(v + voff));
     B->voff[g + 1] = voff + p->n;
     B->max_u = std::max<int64_t>(B->max_u, p->max_u);
     B->max_nf = std::max<int64_t>(B->max_nf, p->max_nf);
     B->max_cap = std::max<int64_t>(B->max_cap, p->cap);
-    B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce;
-    B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce;
+    // the slot tables are read once per launch pair, by the part kernel or the reduction
+    B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce + 4 * p->n_slots;
+    B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce + 4 * p->n_slots;
     eoff += p->m;
     foff += C;
     lofs_off += nloff;
@@ -166,6 +172,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   B->m = eoff;
   B->n = B->voff[n_graphs];
   B->R = rbase;
+  B->vmajor = int64_t(sidx.size()) > 4 * B->R;
   B->n_heavy = int64_t(heavy.size());
   B->n_iso = int64_t(iso.size());
   if (B->k >= (int64_t(1) << 31) || B->n >= (int64_t(1) << 31) || B->m >= (int64_t(1) << 31)) {
@@ -207,6 +214,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   L.fid = take(fid.size() * 4);
   L.rvid = take(rvid.size() * 4);
   L.roff = take(roff.size() * 4);
+  L.sidx = take(sidx.size() * 4);
   L.rslot = take(rslot.size() * 4);
   L.heavy = take(heavy.size() * 4);
   L.iso = take(iso.size() * 4);
@@ -223,6 +231,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   put(L.fid, fid.data(), fid.size() * 4);
   put(L.rvid, rvid.data(), rvid.size() * 4);
   put(L.roff, roff.data(), roff.size() * 4);
+  put(L.sidx, sidx.data(), sidx.size() * 4);
   put(L.rslot, rslot.data(), rslot.size() * 4);
   put(L.heavy, heavy.data(), heavy.size() * 4);
   put(L.iso, iso.data(), iso.size() * 4);

@@ -46,7 +46,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
-  size_t rvid = 0, roff = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
+  size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
   size_t total = 0;
 };
 
@@ -60,7 +60,8 @@ struct DevPlan {
   const int32_t *fid;
   const int32_t *rvid;
   const int32_t *roff;
-  const int32_t *rslot;
+  const int32_t *sidx;   // vertex-major workspace: slot of each foreign entry (else NULL)
+  const int32_t *rslot;  // part-major workspace: the slots of each replicated vertex (else NULL)
   const int32_t *heavy;
   const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
   const int32_t *eoff;   // [k + 1] first task of every part
@@ -99,7 +100,10 @@ struct epk_plan {
   int32_t pipe = 0;
   int64_t lds_pipe_fwd = 0, lds_pipe_fwd_qn = 0, lds_pipe_bwd = 0;
   int64_t grid_pipe_fwd = 0, grid_pipe_fwd_qn = 0, grid_pipe_bwd = 0;
+  // bytes without the slot tables; see plan_bytes
   int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
+  int64_t n_slots = 0;  // foreign entries of the reduced class = workspace rows
+  bool vmajor = false;  // workspace layout: vertex-major (true) or part-major
   void *d_image = nullptr;
 };
 
@@ -111,6 +115,7 @@ struct epk_batch {
   epk::ImageLayout lay;
   size_t ws_bytes = 0;
   int64_t R = 0, n_heavy = 0, n_iso = 0, max_u = 0, max_nf = 0, max_cap = 0, wg = 256;
+  bool vmajor = false;
   int64_t grid_fwd = 0, grid_bwd = 0;  // pipelined persistent grids
   int64_t lds_fwd = 0, lds_bwd = 0, bytes_fwd = 0, bytes_bwd = 0;
   void *d_image = nullptr;
@@ -118,10 +123,11 @@ struct epk_batch {
 
 namespace epk {
 // LDS bytes of the FLUX5 kernels for a given part shape (must match the kernels' carve-up).
-int64_t flux_fwd_lds(int64_t max_u, int64_t cap, bool qnew);
-int64_t flux_bwd_lds(int64_t max_u, int64_t cap);
+int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool qnew);
+int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap);
 int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew);
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
+int64_t plan_bytes(const epk_plan *p, int which);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
 DevPlan dev_plan(const epk_plan *p);
 DevPlan dev_batch(const epk_batch *b);

@@ -213,6 +213,29 @@ __device__ __forceinline__ void stage_state(const PartHdr &h, const float *__res
   dma_rows<5>(dst + h.nown * 5, src, ids, h.nf, tid, nt);
 }
 
+// A part's foreign partials (nf rows of 5) to their workspace slots.
+// Part-major workspace (sidx NULL): one contiguous block at the part's slot
+// offset.  Vertex-major: sidx (in LDS) gives each foreign entry's slot, so
+// that the reduction reads each vertex's slots as one contiguous run.
+__device__ __forceinline__ void write_slots(const PartHdr &h, const float *src, const int32_t *sidx,
+                                            float *__restrict__ ws, int tid, int nt) {
+  if (!sidx) {
+    float *wo = ws + int64_t(h.f0) * 5;
+    for (int d = tid; d < h.nf * 5; d += nt) wo[d] = src[d];
+    return;
+  }
+  for (int d = tid; d < h.nf * 5; d += nt) {
+    const int i = d / 5;
+    ws[int64_t(sidx[i]) * 5 + (d - 5 * i)] = src[d];
+  }
+}
+
+// The slot indices of a part's foreign entries (vertex-major workspace only).
+__device__ __forceinline__ void stage_sidx(const DevPlan &P, const PartHdr &h, int32_t *sidx, int tid, int nt) {
+  if (P.sidx)
+    dma_block(reinterpret_cast<float *>(sidx), reinterpret_cast<const float *>(P.sidx + h.f0), h.nf, tid, nt);
+}
+
 // Forward compute stage.  st holds the part's states; the per-vertex sums go
 // to acc (acc may be st when q_new is not written); flx: cap * 5 floats.
 template <int G, int EPT>
@@ -269,15 +292,15 @@ __device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, f
 // Forward writes of a computed part: owned sums (and q_new) to the output,
 // foreign sums to the part's workspace slots.
 template <bool QNEW>
-__device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, const float *acc, float *__restrict__ r,
-                                          float *__restrict__ qn, float dt, float *__restrict__ ws, int tid, int nt) {
+__device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, const float *acc, const int32_t *sidx,
+                                          float *__restrict__ r, float *__restrict__ qn, float dt,
+                                          float *__restrict__ ws, int tid, int nt) {
   float *ro = r + int64_t(h.own0) * 5;
   for (int d = tid; d < h.nown * 5; d += nt) {
     ro[d] = acc[d];
     if constexpr (QNEW) qn[int64_t(h.own0) * 5 + d] = st[d] + dt * acc[d];
   }
-  float *wo = ws + int64_t(h.f0) * 5;
-  for (int d = tid; d < h.nf * 5; d += nt) wo[d] = acc[h.nown * 5 + d];
+  write_slots(h, acc + h.nown * 5, sidx, ws, tid, nt);
 }
 
 // Adjoint compute stage.  st: states, gs: upstream gradients (overwritten by
@@ -338,18 +361,18 @@ __device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, f
   lds_sync();
 }
 
-__device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, float *__restrict__ gq,
-                                          float *__restrict__ ws, int tid, int nt) {
+__device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, const int32_t *sidx,
+                                          float *__restrict__ gq, float *__restrict__ ws, int tid, int nt) {
   float *go = gq + int64_t(h.own0) * 5;
   for (int d = tid; d < h.nown * 5; d += nt) go[d] = gs[d];
-  float *wo = ws + int64_t(h.f0) * 5;
-  for (int d = tid; d < h.nf * 5; d += nt) wo[d] = gs[h.nown * 5 + d];
+  write_slots(h, gs + h.nown * 5, sidx, ws, tid, nt);
 }
 
 // ---- direct kernels: one part per workgroup
 
 // LDS: st[max_u][5] | (QNEW: acc[max_u][5]) | flx[cap][5] (the ids until the
-// flux stage) | inc[2 cap] u16 | lo[max_u + 2] u16.
+// flux stage) | inc[2 cap] u16 | lo[nlo] u16 | sidx[max_nf], nlo = max_u + 2
+// rounded up to even.
 template <int G, bool QNEW, int EPT>
 __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
                                                         float *__restrict__ qn, float dt, float *__restrict__ ws,
@@ -363,9 +386,11 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   float *flx = (QNEW ? acc : st) + P.max_u * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
   uint16_t *lo = inc + 2 * P.cap;
+  int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
   int32_t *ids = reinterpret_cast<int32_t *>(flx);
   const PartHdr h = load_hdr(P, part);
   stage_ids(P, h, ids, tid, nt);
+  stage_sidx(P, h, sidx, tid, nt);
   uint32_t ew[EPT];
   float4 eg[EPT];
   load_edges<G, EPT>(P, h, tid, nt, ew, eg);
@@ -375,11 +400,11 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   wait_staged();
   compute_fwd<G, EPT>(h, st, acc, flx, inc, lo, ew, eg, tid, nt);
-  write_fwd<QNEW>(h, st, acc, r, qn, dt, ws, tid, nt);
+  write_fwd<QNEW>(h, st, acc, P.sidx ? sidx : nullptr, r, qn, dt, ws, tid, nt);
 }
 
 // LDS: st[max_u][5] | gs[max_u][5] | vu[cap][5] (the ids until the flux
-// stage) | vv[cap][5] | inc | lo.
+// stage) | vv[cap][5] | inc | lo | sidx.
 template <int G, int EPT>
 __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *__restrict__ q,
                                                         const float *__restrict__ gr, float *__restrict__ gq,
@@ -394,9 +419,11 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   float *vv = vu + P.cap * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(vv + P.cap * 5);
   uint16_t *lo = inc + 2 * P.cap;
+  int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
   int32_t *ids = reinterpret_cast<int32_t *>(vu);
   const PartHdr h = load_hdr(P, part);
   stage_ids(P, h, ids, tid, nt);
+  stage_sidx(P, h, sidx, tid, nt);
   uint32_t ew[EPT];
   float4 eg[EPT];
   load_edges<G, EPT>(P, h, tid, nt, ew, eg);
@@ -408,7 +435,7 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   dma_rows<5>(gs + h.nown * 5, gr, ids, h.nf, tid, nt);
   wait_staged();
   compute_bwd<G, EPT>(h, st, gs, vu, vv, inc, lo, ew, eg, tid, nt);
-  write_bwd(h, gs, gq, ws, tid, nt);
+  write_bwd(h, gs, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
 }
 
 // ---- pipelined persistent kernels
@@ -454,8 +481,8 @@ __device__ __forceinline__ PartHdr hdr_unpack(int v) {
 
 // LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):
 // st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | (q_new: acc[max_u][5]) |
-// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
-// lo[2][nlo] u16.  Buffers are addressed by arithmetic on the one LDS base,
+// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | sidx[2][max_nf] |
+// inc[2][2 cap] u16 | lo[2][nlo] u16.  Buffers are addressed by arithmetic on the one LDS base,
 // so every pointer stays an LDS pointer (no indexed pointer arrays).
 struct PipeLds {
   float *base;
@@ -466,11 +493,12 @@ struct PipeLds {
   __device__ float *f0() const { return base + o_f0; }
   __device__ float *f1() const { return base + o_f1; }
   __device__ int32_t *ids(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + b * nf; }
+  __device__ int32_t *sidx(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + (2 + b) * nf; }
   __device__ uint16_t *inc(int b) const {
-    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + b * (2 * cap);
+    return reinterpret_cast<uint16_t *>(base + o_ids + 4 * nf) + b * (2 * cap);
   }
   __device__ uint16_t *lo(int b) const {
-    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + 4 * cap + b * nlo;
+    return reinterpret_cast<uint16_t *>(base + o_ids + 4 * nf) + 4 * cap + b * nlo;
   }
 };
 
@@ -516,6 +544,7 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
   hv = hdr_lanes(P, pipe_part(P.k, 2, swizzle));
   stage_ids(P, h1, L.ids(1), tid, nt);
   stage_state(h0, q, L.st(0), L.ids(0), tid, nt);
+  stage_sidx(P, h0, L.sidx(0), tid, nt);
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
@@ -527,10 +556,12 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
-    write_fwd<QNEW>(hp, L.st(nb), QNEW ? L.acc() : L.st(nb), r, qn, dt, ws, tid, nt);  // W(t-1)
-    lds_sync();                                           // buffer nb and acc are free again
+    write_fwd<QNEW>(hp, L.st(nb), QNEW ? L.acc() : L.st(nb), P.sidx ? L.sidx(nb) : nullptr, r, qn, dt, ws, tid,
+                    nt);  // W(t-1)
+    lds_sync();                                           // buffers nb and acc are free again
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));   // H(t+3)
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);     // B(t+1)
+    stage_sidx(P, h1, L.sidx(nb), tid, nt);
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);                  // A(t+2)
@@ -545,7 +576,7 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
     }
   }
   const int pb = (t + 1) & 1;  // buffer of part t-1
-  write_fwd<QNEW>(hp, L.st(pb), QNEW ? L.acc() : L.st(pb), r, qn, dt, ws, tid, nt);
+  write_fwd<QNEW>(hp, L.st(pb), QNEW ? L.acc() : L.st(pb), P.sidx ? L.sidx(pb) : nullptr, r, qn, dt, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
 }
 
@@ -570,6 +601,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
   stage_ids(P, h1, L.ids(1), tid, nt);
   stage_state(h0, q, L.st(0), L.ids(0), tid, nt);
   stage_state(h0, gr, L.gs(0), L.ids(0), tid, nt);
+  stage_sidx(P, h0, L.sidx(0), tid, nt);
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
@@ -579,11 +611,12 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
-    write_bwd(hp, L.gs(nb), gq, ws, tid, nt);
+    write_bwd(hp, L.gs(nb), P.sidx ? L.sidx(nb) : nullptr, gq, ws, tid, nt);
     lds_sync();
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);
     stage_state(h1, gr, L.gs(nb), L.ids(nb), tid, nt);
+    stage_sidx(P, h1, L.sidx(nb), tid, nt);
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);
@@ -597,13 +630,14 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
       eg[k] = egn[k];
     }
   }
-  write_bwd(hp, L.gs((t + 1) & 1), gq, ws, tid, nt);
+  write_bwd(hp, L.gs((t + 1) & 1), P.sidx ? L.sidx((t + 1) & 1) : nullptr, gq, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);
 }
 
 // ------------------------------------------------------------------ SpMV
 
-// LDS: xs[max_ux] | ys[max_uy] | per-wave carry keys and values.
+// LDS: xs[max_ux] | ys[max_uy] | ysl[max_uy] (slots of the foreign y) |
+// per-wave carry keys and values.
 __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__restrict__ x, float *__restrict__ y,
                                                     float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
@@ -617,7 +651,8 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   const int ne = int(P.eoff[part + 1] - e0);
   float *xs = smem;
   float *ys = xs + P.max_u;
-  int *tkey = reinterpret_cast<int *>(ys + P.max_uy);
+  int32_t *ysl = reinterpret_cast<int32_t *>(ys + P.max_uy);
+  int *tkey = ysl + P.max_uy;
   float *tval = reinterpret_cast<float *>(tkey + (nt >> 6));
   const int lane = tid & 63, wave = tid >> 6;
 
@@ -627,6 +662,7 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   int32_t *xid = reinterpret_cast<int32_t *>(xs + xn);
   dma_block(xs, x + xo, xn, tid, nt);
   dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.fid + xf0), xnf, tid, nt);
+  if (P.sidx) dma_block(reinterpret_cast<float *>(ysl), reinterpret_cast<const float *>(P.sidx + yf0), ynf, tid, nt);
   const bool valid = tid < ne;
   const int64_t ec = clamp_edge(P, int(e0), ne, tid);
   const uint32_t w = P.eloc[ec];
@@ -663,16 +699,21 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   }
   __syncthreads();
   for (int d = tid; d < yn; d += nt) y[yo + d] = ys[d];
-  float *wo = ws + yf0;
-  for (int d = tid; d < ynf; d += nt) wo[d] = ys[yn + d];
+  if (P.sidx) {
+    for (int d = tid; d < ynf; d += nt) ws[ysl[d]] = ys[yn + d];
+  } else {
+    for (int d = tid; d < ynf; d += nt) ws[yf0 + d] = ys[yn + d];
+  }
 }
 
 // ------------------------------------------------------------------ reduction
 
 // Light vertices (<= kHeavySlots partials): one thread per vertex,
-// r_v = (((own + s_1) + s_2) + ...) in ascending part order.  Heavy vertices:
-// one workgroup each, strided partial sums then a fixed tree.  Untouched
-// vertices are zeroed here as well.
+// r_v = (((own + s_1) + s_2) + ...) in ascending part order; a vertex's slots
+// are one contiguous run of a vertex-major workspace, or found through rslot
+// in a part-major one.  Heavy vertices: one workgroup
+// each, strided partial sums then a fixed tree.  Untouched vertices are
+// zeroed here as well.
 template <int NC, bool QNEW>
 __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restrict__ r, const float *__restrict__ ws,
                                                      const float *__restrict__ q, float *__restrict__ qn, float dt,
@@ -687,16 +728,24 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restric
       float s[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) s[c] = r[o + c];
-      for (int t = s0; t < s1; t += 4) {  // four slot ids per batch of loads
-        int sl[4];
+      if (P.rslot) {
+        for (int t = s0; t < s1; t += 4) {  // four slot ids per batch of loads
+          int sl[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) sl[u] = t + u < s1 ? P.rslot[t + u] : -1;
+          for (int u = 0; u < 4; ++u) sl[u] = t + u < s1 ? P.rslot[t + u] : -1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (sl[u] >= 0) {
+          for (int u = 0; u < 4; ++u)
+            if (sl[u] >= 0) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) s[c] += ws[int64_t(sl[u]) * NC + c];
-          }
+              for (int c = 0; c < NC; ++c) s[c] += ws[int64_t(sl[u]) * NC + c];
+            }
+        }
+      } else {
+        const float *wp = ws + int64_t(s0) * NC;
+        for (int t = 0; t < s1 - s0; ++t) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) s[c] += wp[t * NC + c];
+        }
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -718,7 +767,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restric
   const int64_t base = int64_t(P.rvid[rho]) * NC;
   for (int c = 0; c < NC; ++c) {
     float s = 0.0f;
-    for (int t = s0 + threadIdx.x; t < s1; t += kHeavyBlock) s += ws[int64_t(P.rslot[t]) * NC + c];
+    for (int t = s0 + threadIdx.x; t < s1; t += kHeavyBlock) s += ws[int64_t(P.rslot ? P.rslot[t] : t) * NC + c];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kHeavyBlock / 2; w > 0; w >>= 1) {

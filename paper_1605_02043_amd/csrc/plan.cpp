@@ -31,26 +31,40 @@ namespace epk {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Must match the LDS carve-up of flux_fwd_part / flux_bwd_part.
-int64_t flux_fwd_lds(int64_t max_u, int64_t cap, bool qnew) {
-  const int64_t b = 4 * ((qnew ? 10 : 5) * max_u + 5 * cap) + 2 * (2 * cap + max_u + 2);
+int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool qnew) {
+  const int64_t nlo = (max_u + 3) & ~int64_t(1);
+  const int64_t b = 4 * ((qnew ? 10 : 5) * max_u + 5 * cap) + 2 * (2 * cap + nlo) + 4 * max_nf;
   return (b + 15) & ~int64_t(15);
 }
-int64_t flux_bwd_lds(int64_t max_u, int64_t cap) {
-  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + max_u + 2);
+int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap) {
+  const int64_t nlo = (max_u + 3) & ~int64_t(1);
+  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + nlo) + 4 * max_nf;
   return (b + 15) & ~int64_t(15);
 }
 // Mirror of the device carve-up of the pipelined kernels: two state buffers
 // (two more for the adjoint's gradients), q_new sums, one (two) edge value
-// buffer(s), two id buffers, two incidence lists and two offset lists.
+// buffer(s), two id and two slot-index buffers, two incidence lists and two
+// offset lists.
 int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew) {
   const int64_t su = 5 * max_u, sf = 5 * cap, nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
+  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 4 * max_nf +
                     2 * (4 * cap + 2 * nlo);
   return (b + 15) & ~int64_t(15);
 }
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
-  const int64_t b = 4 * (max_ux + max_uy) + 8 * (wg / 64);
+  const int64_t b = 4 * (max_ux + 2 * max_uy) + 8 * (wg / 64);
   return (b + 15) & ~int64_t(15);
+}
+
+// Algorithmic bytes of one launch under the plan's workspace layout:
+// which = 0 forward part kernel, 1 adjoint part kernel, 2 reduction.  The
+// vertex-major layout adds the slot-index reads to the part kernels, the
+// part-major one the slot-list reads to the reduction.
+int64_t plan_bytes(const epk_plan *p, int which) {
+  const int64_t ids = 4 * p->n_slots;
+  if (which == 0) return p->bytes_fwd_kernel + (p->vmajor ? ids : 0);
+  if (which == 1) return p->kind == EPK_FLUX5 ? p->bytes_bwd_kernel + (p->vmajor ? ids : 0) : 0;
+  return p->bytes_reduce + (p->vmajor ? 0 : ids);
 }
 
 namespace {
@@ -305,11 +319,16 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->max_nf = max_nf;
 
     // ---- reduction tables: for each replicated vertex of the reduced class,
-    // its slots (non-owner parts) in ascending part order.
+    // its slots (non-owner parts) in ascending part order.  Two workspace
+    // layouts: part-major (a part writes its foreign partials as one block;
+    // rslot lists, vertex by vertex, where the reduction finds them) and
+    // vertex-major (a vertex's slots side by side; sidx gives each part's
+    // entries their slot).  Both tables are in the image; the layout in use
+    // is chosen per plan (epk_plan_set_slot_layout).
     const int32_t nred = kind == EPK_SPMV ? n - P->n_x : n;
     std::vector<int32_t> scount(size_t(nred), 0);
     for (int32_t v : red_foreign) scount[v]++;
-    std::vector<int32_t> rvid, roff(1, 0), rslot(red_foreign.size()), heavy;
+    std::vector<int32_t> rvid, roff(1, 0), sidx(red_foreign.size()), rslot(red_foreign.size()), heavy;
     std::vector<int32_t> start(size_t(nred), 0);
     for (int32_t v = 0; v < nred; ++v) {
       if (scount[v] == 0) continue;
@@ -321,9 +340,12 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::fill(scount.begin(), scount.end(), 0);
     for (size_t s = 0; s < red_foreign.size(); ++s) {  // part-major walk: ascending part order
       const int32_t v = red_foreign[s];
-      rslot[start[v] + scount[v]++] = int32_t(s);
+      sidx[s] = start[v] + scount[v]++;
+      rslot[sidx[s]] = int32_t(s);
     }
     P->R = int64_t(rvid.size());
+    P->n_slots = int64_t(red_foreign.size());
+    P->vmajor = P->n_slots > 4 * P->R;  // gather-heavy reduction: many slots per vertex
     P->n_heavy = int64_t(heavy.size());
     P->n_out = nred;
     P->n_active_out = kind == EPK_SPMV ? active[1] - P->n_x : active[0];
@@ -346,6 +368,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.fid = take(fid.size() * 4);
     L.rvid = take(rvid.size() * 4);
     L.roff = take(roff.size() * 4);
+    L.sidx = take(sidx.size() * 4);
     L.rslot = take(rslot.size() * 4);
     L.heavy = take(heavy.size() * 4);
     L.total = std::max<size_t>(off, 256);
@@ -360,6 +383,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     put(P->image, L.fid, fid);
     put(P->image, L.rvid, rvid);
     put(P->image, L.roff, roff);
+    put(P->image, L.sidx, sidx);
     put(P->image, L.rslot, rslot);
     put(P->image, L.heavy, heavy);
     const int nc = kind == EPK_SPMV ? 1 : 5;
@@ -369,9 +393,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     const int64_t C = P->stats.cost, Lds = P->stats.loads, R = P->R;
     const int64_t Cred = int64_t(red_foreign.size());
     if (kind == EPK_FLUX5) {
-      P->lds_fwd = flux_fwd_lds(P->max_u, cap, false);
-      P->lds_fwd_qn = flux_fwd_lds(P->max_u, cap, true);
-      P->lds_bwd = flux_bwd_lds(P->max_u, cap);
+      P->lds_fwd = flux_fwd_lds(P->max_u, P->max_nf, cap, false);
+      P->lds_fwd_qn = flux_fwd_lds(P->max_u, P->max_nf, cap, true);
+      P->lds_bwd = flux_bwd_lds(P->max_u, P->max_nf, cap);
       P->lds_pipe_fwd = flux_pipe_lds(P->max_u, P->max_nf, cap, false, false);
       P->lds_pipe_fwd_qn = flux_pipe_lds(P->max_u, P->max_nf, cap, false, true);
       P->lds_pipe_bwd = flux_pipe_lds(P->max_u, P->max_nf, cap, true, false);
@@ -379,7 +403,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
       P->bytes_bwd_kernel = meta + 40 * Lds + 20 * na + 20 * C;
-      P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 20 * Cred + 40 * R + 20 * (nred - na);
+      P->bytes_reduce = 4 * R + 4 * (R + 1) + 20 * Cred + 40 * R + 20 * (nred - na);
       P->bytes_reduce_qnew = P->bytes_reduce + 40 * R + 40 * (nred - na);
     } else {
       P->lds_fwd = P->lds_bwd = spmv_lds(P->max_u, P->max_uy, P->wg);
@@ -392,7 +416,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       const int64_t na = P->n_active_out;
       P->bytes_fwd_kernel = 32 * k + 4 * m + 4 * m + 4 * Cx + 4 * Lxs + 4 * na + 4 * Cred;
       P->bytes_bwd_kernel = 0;
-      P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 4 * Cred + 8 * R + 4 * (nred - na);
+      P->bytes_reduce = 4 * R + 4 * (R + 1) + 4 * Cred + 8 * R + 4 * (nred - na);
       P->bytes_reduce_qnew = P->bytes_reduce;
     }
     if (P->lds_fwd > kMaxLdsBytes || P->lds_fwd_qn > kMaxLdsBytes || P->lds_bwd > kMaxLdsBytes) {
@@ -473,21 +497,23 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s) {
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
   epk::clear_error();
   if (!p || !info) return epk::fail(EPK_EINVAL, "NULL argument");
-  const int64_t v[14] = {p->k,
+  const int64_t bf = epk::plan_bytes(p, 0), bb = epk::plan_bytes(p, 1), br = epk::plan_bytes(p, 2);
+  const int64_t v[15] = {p->k,
                          p->lds_fwd,
                          p->lds_bwd,
                          p->wg,
                          p->ncls,
-                         p->bytes_fwd_kernel + p->bytes_reduce,
-                         p->bytes_bwd_kernel + p->bytes_reduce,
-                         p->bytes_fwd_kernel,
-                         p->bytes_bwd_kernel,
+                         bf + br,
+                         p->kind == EPK_FLUX5 ? bb + br : 0,
+                         bf,
+                         bb,
                          p->max_nf,
                          p->pipe,
                          p->pipe ? p->grid_pipe_fwd : 0,
                          p->pipe ? p->grid_pipe_bwd : 0,
-                         p->lds_pipe_bwd};
-  for (int32_t i = 0; i < n_info && i < 14; ++i) info[i] = v[i];
+                         p->lds_pipe_bwd,
+                         p->vmajor ? 1 : 0};
+  for (int32_t i = 0; i < n_info && i < 15; ++i) info[i] = v[i];
   return EPK_OK;
 }
 
@@ -506,6 +532,14 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   }
   if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
   p->pipe = 0;  // the pipelined grid depends on both: set it again
+  return EPK_OK;
+}
+
+int epk_plan_set_slot_layout(epk_plan *p, int32_t layout) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (layout < -1 || layout > 1) return epk::fail(EPK_EINVAL, "layout must be -1, 0 or 1");
+  p->vmajor = layout < 0 ? p->n_slots > 4 * p->R : layout == 1;
   return EPK_OK;
 }
 

@@ -179,3 +179,21 @@ def test_plan_handles_empty_graph():
     P = Plan(np.zeros((0, 2), np.int32), 5, 16, np.zeros((0, 4), np.float32))
     assert P.stats["n_parts"] == 0 and P.stats["loads"] == 0
     assert sorted(P.perm().tolist()) == list(range(5))
+
+
+def test_slot_layout_choice_and_bytes():
+    """Meshes keep the part-major workspace, power-law SpMV takes the vertex-major one;
+    the slot tables are counted once per forward either way."""
+    T = gen.tet_mesh(8, 8, 8, seed=0)
+    P = Plan(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
+    a = P.info()
+    assert a["vertex_major"] == 0
+    P.set_slot_layout(1)
+    b = P.info()
+    assert b["vertex_major"] == 1 and b["bytes_fwd"] == a["bytes_fwd"] and b["bytes_fwd_kernel"] > a["bytes_fwd_kernel"]
+    with pytest.raises(_lib.EpkError):
+        P.set_slot_layout(2)
+    R = gen.rmat(scale=12, n_edges=60_000, seed=1)
+    g = spmv_graph(R, R["shuffle"])
+    S = Plan(g["edges"], g["n"], 256, g["w"], kind="spmv", n_x=g["n_x"])
+    assert S.info()["vertex_major"] == 1
