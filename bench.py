@@ -73,6 +73,7 @@ def _args():
                     help="extra steps timed after a 1 GiB cache scrub each (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the random and greedy vertex-cut orders")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -377,6 +378,20 @@ def main():
                                 "algorithmic_bytes_per_edge": default["bytes_per_edge_fwd_bwd"]}
         out["algorithmic_bytes_per_edge"]["default"] = default["bytes_per_edge_fwd_bwd"]
         out["speedup_vs_default_order"] = default["wall_ms_per_step"] / ep["wall_ms_per_step"]
+    if not args.no_baselines:
+        # the related work's vertex-cut placements (random, greedy) with the same capacity and kernels
+        out["baseline_orders"] = {}
+        cold, COLD_STEPS = COLD_STEPS, 0
+        for order in ("greedy", "random"):
+            b = run_order(G, order, args.cap, min(args.steps, 20), args.warmup, torch, args.wg, args.swizzle, args.pipe)
+            bst = b["stats"]
+            out["baseline_orders"][order] = {"value": b["edges_per_s"], "ms_per_step": b["wall_ms_per_step"],
+                                             "loads_per_edge": bst["loads"] / m, "cost": bst["cost"],
+                                             "algorithmic_bytes_per_edge": b["bytes_per_edge_fwd_bwd"],
+                                             "partition_seconds": bst["partition_seconds"]}
+            print(f"# {order}: {out['baseline_orders'][order]}", file=sys.stderr, flush=True)
+            del b
+        COLD_STEPS = cold
     if traffic:
         out["dram_bytes_per_edge"] = {o: sum(v["bytes"] * v["launches_per_step"] for v in traffic[o].values()) / m
                                       for o in ("ep", "default")}

@@ -60,7 +60,14 @@ typedef enum {
   EPK_ORDER_INPUT = 1,
   /* single-pass greedy growing on the same transform: k = ceil(m / cap),
    * parts 0..k-2 hold exactly cap edges, tasks in placement order */
-  EPK_ORDER_GGP = 2
+  EPK_ORDER_GGP = 2,
+  /* baselines from the paper's related work (PowerGraph's vertex cuts), same
+   * k = ceil(m / cap) and capacity: random placement (edges sorted by the
+   * SplitMix64 hash of their id, consecutive blocks of cap) and greedy
+   * placement (edges in id order onto the least loaded part already holding
+   * an endpoint, preferring parts holding both); see baselines.cpp */
+  EPK_ORDER_RANDOM = 3,
+  EPK_ORDER_GREEDY = 4
 } epk_order;
 
 typedef enum {

@@ -21,25 +21,32 @@ GPU Caching Problems"):
                 paper names the interaction's inputs in Section 3.1 but gives no
                 formula; the formula here is this project's reading).
 * ``spmv``    - y_i += w * x_j over the bipartite SpMV graph (Section 5.2).
+* ``baselines`` - PowerGraph's random and greedy vertex-cut placements, the
+                partitioners the paper's related work quotes (Section 3).
 * ``brute``   - exhaustive optimal partitions for tiny graphs (Theorems 1-2).
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
-CPU tests.  The exact output of ``multilevel.partition``, ``ggp.partition``
-and ``cpack.layout`` beyond those pins is parity unpinned: it is fixed by
-their specification and checked only by two independent implementations
-agreeing bit for bit.
+CPU tests.  The exact output of ``multilevel.partition``, ``ggp.partition``,
+the two ``baselines`` and ``cpack.layout`` beyond those pins is parity
+unpinned: it is fixed by their specification and checked only by two
+independent implementations agreeing bit for bit.
 """
 
-from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute  # noqa: F401
+from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines  # noqa: F401
 
 
 def partition(edges, n, cap, order="ep"):
     """(part, task_order) for an order: 'ep' (multilevel, the default), 'ggp'
-    (single-pass greedy growing) or 'input' (consecutive blocks)."""
+    (single-pass greedy growing), 'input' (consecutive blocks), or the
+    baselines 'random' and 'greedy'."""
     if order == "ep":
         part, task, _ = multilevel.partition(edges, n, cap)
         return part, task
     if order == "ggp":
         return ggp.partition(edges, n, cap, order="ep")
+    if order == "random":
+        return baselines.random_partition(len(edges), cap)
+    if order == "greedy":
+        return baselines.greedy_partition(edges, n, cap)
     return ggp.partition(edges, n, cap, order="input")

@@ -9,7 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libepk.so")
 
 EPK_OK, EPK_EINVAL, EPK_ERANGE, EPK_EHIP, EPK_ESTATE, EPK_ENOMEM = 0, -1, -2, -3, -4, -5
-ORDER = {"ep": 0, "input": 1, "ggp": 2}
+ORDER = {"ep": 0, "input": 1, "ggp": 2, "random": 3, "greedy": 4}
 KIND = {"flux5": 0, "spmv": 1}
 
 

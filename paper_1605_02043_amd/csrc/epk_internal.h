@@ -33,6 +33,11 @@ void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::v
 void greedy_growing(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
                     std::vector<int32_t> &task);
 void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
+// baselines.cpp: PowerGraph's random and greedy vertex-cut placements
+uint64_t splitmix64(uint64_t x);
+void random_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
+void greedy_vertex_cut(int32_t n, int64_t m, const int32_t *uv, int32_t cap, std::vector<int32_t> &part,
+                       std::vector<int32_t> &task);
 int64_t multilevel_parts(int64_t m, int32_t cap);
 void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
                 std::vector<int32_t> &task);

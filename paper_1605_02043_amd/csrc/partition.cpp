@@ -208,8 +208,7 @@ void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const s
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
   if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
-  if (order != EPK_ORDER_EP && order != EPK_ORDER_INPUT && order != EPK_ORDER_GGP)
-    return fail(EPK_EINVAL, "unknown order");
+  if (order < EPK_ORDER_EP || order > EPK_ORDER_GREEDY) return fail(EPK_EINVAL, "unknown order");
   std::memset(&st, 0, sizeof(st));
   try {
     const auto t0 = std::chrono::steady_clock::now();
@@ -219,6 +218,10 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
     int64_t k = m ? (m + cap - 1) / cap : 0;
     if (order == EPK_ORDER_INPUT) {
       input_order(m, cap, part, task);
+    } else if (order == EPK_ORDER_RANDOM) {
+      random_order(m, cap, part, task);
+    } else if (order == EPK_ORDER_GREEDY) {
+      greedy_vertex_cut(g->n_vertices, m, g->edge_uv, cap, part, task);
     } else {
       std::vector<int32_t> nbr;
       contracted_links(m, g->edge_uv, inc, nbr);

@@ -105,7 +105,7 @@ def _check_parity(edges, n, cap, order="ep", n_x=None):
 
 @settings(max_examples=60, deadline=None)
 @given(st.integers(2, 60), st.integers(0, 200), st.integers(1, 40), st.integers(0, 10_000),
-       st.sampled_from(["ep", "ggp", "input"]))
+       st.sampled_from(["ep", "ggp", "input", "random", "greedy"]))
 def test_partition_parity_random(n, m, cap, seed, order):
     rng = np.random.default_rng(seed)
     u = rng.integers(0, n, m)
@@ -116,7 +116,7 @@ def test_partition_parity_random(n, m, cap, seed, order):
 
 def test_partition_parity_grid64_and_fig1(golden_dir):
     G = gen.grid2d(64, 64, seed=0)
-    for order in ("ep", "ggp", "input"):
+    for order in ("ep", "ggp", "input", "random", "greedy"):
         _check_parity(G["edges"], G["n"], 256, order)
     import json
 
@@ -138,6 +138,8 @@ def test_partition_parity_rmat_bipartite():
     R = gen.rmat(scale=12, n_edges=40_000, seed=2)
     g = spmv_graph(R, R["shuffle"])
     _check_parity(g["edges"], g["n"], 256)
+    _check_parity(g["edges"][:8000], g["n"], 64, "greedy")
+    _check_parity(g["edges"], g["n"], 256, "random")
 
 
 def _check_layout(edges, n, cap, geom, kind="flux5", n_x=0, order="ep"):

@@ -380,3 +380,63 @@ def test_multilevel_beats_single_pass_on_meshes():
         pm, _, k = multilevel.partition(E, n, 128)
         pg, _ = ggp.partition(E, n, 128)
         assert cost.partition_cost(E, n, pm, k)["loads"] < cost.partition_cost(E, n, pg)["loads"]
+
+
+# ------------------------------------------------------------------ baselines (PowerGraph vertex cuts)
+
+def test_splitmix64_published_values():
+    """The first outputs of SplitMix64 seeded with 0 (the generator's published sequence)."""
+    from oracle.baselines import splitmix64
+
+    g = 0x9E3779B97F4A7C15
+    assert splitmix64(0) == 0xE220A8397B1DCDAF
+    assert splitmix64(g) == 0x6E789E6AA1B965F4
+    assert splitmix64(2 * g % (1 << 64)) == 0x06C45D188009454F
+
+
+@pytest.mark.parametrize("m,cap", [(0, 4), (1, 4), (17, 4), (64, 8), (100, 7)])
+def test_random_baseline_is_balanced_permutation(m, cap):
+    from oracle.baselines import random_partition
+
+    part, task = random_partition(m, cap)
+    assert sorted(task.tolist()) == list(range(m))
+    k = -(-m // cap)
+    sizes = np.bincount(part, minlength=k) if m else np.zeros(0, int)
+    assert all(sizes[:-1] == cap) if k > 1 else True
+    assert (part[task] == np.arange(m) // cap).all()
+
+
+def test_greedy_baseline_capacity_and_closed_forms():
+    from oracle.baselines import greedy_partition
+
+    # disjoint components of exactly cap edges, listed one after another: cost 0
+    cap, comps = 6, 5
+    E = []
+    for c in range(comps):
+        base = 10 * c
+        E += [(base + i, base + i + 1) for i in range(cap)]  # a path of cap edges
+    E = np.array(E)
+    part, task = greedy_partition(E, 10 * comps, cap)
+    assert cost.partition_cost(E, 10 * comps, part, comps)["cost"] == 0
+    # a path in order: consecutive blocks, the optimum k - 1
+    P = np.array([(i, i + 1) for i in range(40)])
+    part, _ = greedy_partition(P, 41, 8)
+    assert cost.partition_cost(P, 41, part, 5)["cost"] == 4
+    # a star: every part holds the hub, cost k - 1 whatever the placement
+    S = np.array([(0, i) for i in range(1, 30)])
+    part, _ = greedy_partition(S, 30, 4)
+    assert np.bincount(part).max() <= 4
+    assert cost.partition_cost(S, 30, part, 8)["cost"] == 7
+
+
+def test_baselines_rank_below_ep_on_a_mesh():
+    """Sanity, not a pin: on a 2D mesh the transform-based order beats greedy, which beats random."""
+    import gen
+    import oracle
+
+    G = gen.grid2d(24, 24, seed=0)
+    k = {}
+    for order in ("ep", "greedy", "random"):
+        part, _ = oracle.partition(G["edges"], G["n"], 64, order)
+        k[order] = cost.partition_cost(G["edges"], G["n"], part, int(part.max()) + 1)["cost"]
+    assert k["ep"] < k["greedy"] < k["random"]
