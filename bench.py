@@ -65,6 +65,8 @@ def _args():
     ap.add_argument("--cap", type=int, default=256)
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
+    ap.add_argument("--staging", type=int, default=1,
+                    help="1: stage each part's states in LDS; 0: the cache-only variant (states read through L1/L2)")
     ap.add_argument("--pipe", type=int, default=0,
                     help="pipelined persistent launch, workgroups per CU (-1: as many as fit, 0: one per part)")
     ap.add_argument("--eager", action="store_true",
@@ -124,7 +126,7 @@ def C_void(x):
     return ctypes.c_void_p(x)
 
 
-def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1):
+def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, staging=1):
     from paper_1605_02043_amd import Plan
 
     import gen
@@ -133,7 +135,9 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1):
     P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order)
     P.set_launch(wg, swizzle)
     P.upload("cuda")
-    if pipe:
+    if not staging:
+        P.set_staging(0)
+    elif pipe:
         P.set_pipeline(pipe)
     plan_s = time.perf_counter() - t0
     perm = P.perm()
@@ -313,11 +317,12 @@ def main():
     G = gen.workload(args.workload, seed=0)
     m = len(G["edges"])
     print(f"# workload {args.workload}: n={G['n']} m={m}", file=sys.stderr, flush=True)
-    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe)
+    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe, args.staging)
     print(f"# ep: {ep['wall_ms_per_step']:.4f} ms/step kernels {ep['kernel_ms']}", file=sys.stderr, flush=True)
     default = None
     if not args.no_default_order:
-        default = run_order(G, "input", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe)
+        default = run_order(G, "input", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe,
+                            args.staging)
         print(f"# default: {default['wall_ms_per_step']:.4f} ms/step kernels {default['kernel_ms']}", file=sys.stderr,
               flush=True)
     # dominant kernel of the partitioned step
@@ -357,6 +362,7 @@ def main():
             "timing": "eager launches" if args.eager else "hip-graph replay of the timed steps",
             "launch": (f"pipelined persistent, grid {ep['info']['grid_pipe_fwd']} fwd / {ep['info']['grid_pipe_bwd']} bwd"
                        if ep["info"]["pipe"] else "one workgroup per part"),
+            "staging": "LDS" if ep["info"]["staging"] else "caches only (no LDS staging of states)",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -378,12 +384,24 @@ def main():
                                 "algorithmic_bytes_per_edge": default["bytes_per_edge_fwd_bwd"]}
         out["algorithmic_bytes_per_edge"]["default"] = default["bytes_per_edge_fwd_bwd"]
         out["speedup_vs_default_order"] = default["wall_ms_per_step"] / ep["wall_ms_per_step"]
+    if not args.no_baselines and args.staging:
+        # the paper's cache-only alternative to LDS staging, same plan and order
+        cold, COLD_STEPS = COLD_STEPS, 0
+        v = run_order(G, "ep", args.cap, min(args.steps, 20), args.warmup, torch, args.wg, args.swizzle, 0, 0)
+        out["variants"] = {"cache_only": {"value": v["edges_per_s"], "ms_per_step": v["wall_ms_per_step"],
+                                          "kernels": {nm: {"ms": v["kernel_loop_ms"][nm],
+                                                           "GB/s": algo[nm] / (v["kernel_loop_ms"][nm] * 1e-3) / 1e9}
+                                                      for nm in v["kernel_loop_ms"]}}}
+        print(f"# cache-only: {out['variants']['cache_only']}", file=sys.stderr, flush=True)
+        del v
+        COLD_STEPS = cold
     if not args.no_baselines:
         # the related work's vertex-cut placements (random, greedy) with the same capacity and kernels
         out["baseline_orders"] = {}
         cold, COLD_STEPS = COLD_STEPS, 0
         for order in ("greedy", "random"):
-            b = run_order(G, order, args.cap, min(args.steps, 20), args.warmup, torch, args.wg, args.swizzle, args.pipe)
+            b = run_order(G, order, args.cap, min(args.steps, 20), args.warmup, torch, args.wg, args.swizzle, args.pipe,
+                          args.staging)
             bst = b["stats"]
             out["baseline_orders"][order] = {"value": b["edges_per_s"], "ms_per_step": b["wall_ms_per_step"],
                                              "loads_per_edge": bst["loads"] / m, "cost": bst["cost"],

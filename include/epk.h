@@ -144,8 +144,9 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s);
  * [7] = forward-kernel-only bytes, [8] = adjoint-kernel-only bytes,
  * [9] = max foreign vertices of a part, [10] = pipelined launch setting
  * (0: off), [11] / [12] = its forward / adjoint grid, [13] = its adjoint
- * LDS bytes, [14] = workspace layout in use (0 part-major, 1 vertex-major).
- * The byte counts follow the layout in use.                               */
+ * LDS bytes, [14] = workspace layout in use (0 part-major, 1 vertex-major),
+ * [15] = state staging (1 LDS, 0 caches only).  The byte counts follow the
+ * layout in use.                                                          */
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
  * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
@@ -174,6 +175,13 @@ int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
  * every result bit, is the same under both.  Host only; takes effect at the
  * next launch.                                                            */
 int epk_plan_set_slot_layout(epk_plan *p, int32_t layout);
+/* FLUX5 only: staged = 1 (default) stages each part's vertex states in LDS,
+ * one fetch per distinct vertex (Section 4); staged = 0 runs the paper's
+ * cache-only alternative (Section 5.3's texture-cache variant): the same
+ * parts, task order and packed layout, each edge reading its endpoints'
+ * states from global memory through L1/L2.  Bitwise the same results.
+ * Switches the pipelined launch off.  EPK_ERANGE if its LDS does not fit. */
+int epk_plan_set_staging(epk_plan *p, int32_t staged);
 void epk_plan_destroy(epk_plan *p);
 
 /* ---------------------------------------------------------------- device */

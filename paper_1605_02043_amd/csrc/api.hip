@@ -323,6 +323,7 @@ int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu) {
     return EPK_OK;
   }
   if (p->kind != EPK_FLUX5) return fail(EPK_EINVAL, "the pipelined launch is for FLUX5 plans");
+  if (!p->staging) return fail(EPK_ESTATE, "the pipelined launch stages states: set staging first");
   if (p->wg > 256) return fail(EPK_EINVAL, "the pipelined launch needs a workgroup of at most 256");
   if (p->lds_pipe_fwd_qn > kMaxLdsBytes || p->lds_pipe_bwd > kMaxLdsBytes)
     return fail(EPK_ERANGE, "parts too large for the pipelined launch's LDS buffers");
@@ -363,7 +364,14 @@ static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *
   if (op == EPK_OP_BACKWARD) q_new = nullptr;
   if (stage != 1) {  // -1 runs both
     hipError_t e = hipSuccess;
-    if (op != EPK_OP_SPMV && p->pipe) {
+    if (op != EPK_OP_SPMV && !p->staging) {
+      if (op == EPK_OP_FORWARD)
+        e = launch_flux_cached(P, p->wg, size_t(p->lds_cached_fwd), in, nullptr, out, q_new, dt, ws, false, p->swizzle,
+                               s);
+      else
+        e = launch_flux_cached(P, p->wg, size_t(p->lds_cached_bwd), in, g_r, out, nullptr, 0.f, ws, true, p->swizzle,
+                               s);
+    } else if (op != EPK_OP_SPMV && p->pipe) {
       if (op == EPK_OP_FORWARD)
         e = launch_flux_pipe(P, p->wg, int(q_new ? p->grid_pipe_fwd_qn : p->grid_pipe_fwd),
                              size_t(q_new ? p->lds_pipe_fwd_qn : p->lds_pipe_fwd), in, nullptr, out, q_new, dt, ws,

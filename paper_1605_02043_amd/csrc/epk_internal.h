@@ -103,6 +103,8 @@ struct epk_plan {
   // pipelined persistent launch (FLUX5): workgroups per CU asked for (0: one
   // workgroup per part), LDS bytes and grid sizes of the three kernels
   int32_t pipe = 0;
+  int32_t staging = 1;  // FLUX5: 1 states staged in LDS, 0 read through the caches
+  int64_t lds_cached_fwd = 0, lds_cached_bwd = 0;
   int64_t lds_pipe_fwd = 0, lds_pipe_fwd_qn = 0, lds_pipe_bwd = 0;
   int64_t grid_pipe_fwd = 0, grid_pipe_fwd_qn = 0, grid_pipe_bwd = 0;
   // bytes without the slot tables; see plan_bytes
@@ -131,6 +133,7 @@ namespace epk {
 int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool qnew);
 int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap);
 int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew);
+int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd);
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 int64_t plan_bytes(const epk_plan *p, int which);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);

@@ -12,6 +12,8 @@ hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q,
                            float *ws, int swizzle, hipStream_t s);
 hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
                            int swizzle, hipStream_t s);
+hipError_t launch_flux_cached(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
+                              float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s);
 hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, const float *q, const float *gr,
                             float *out, float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s);
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,

@@ -213,6 +213,72 @@ __device__ __forceinline__ void stage_state(const PartHdr &h, const float *__res
   dma_rows<5>(dst + h.nown * 5, src, ids, h.nf, tid, nt);
 }
 
+// Sum of the signed per-edge fluxes at local vertex i, over its incidence
+// list in ascending (edge, side) order: the first kIncBatch entries, then
+// their rows, each as one batch of LDS reads.
+__device__ __forceinline__ void vertex_sum_fwd(const float *flx, const uint16_t *inc, const uint16_t *lo, int i,
+                                               float s[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] = 0.f;
+  const int t0 = lo[i], t1 = lo[i + 1];
+  // the first kIncBatch entries: their indices, then their rows, each as one
+  // batch of LDS reads; the sum still runs in list order
+  int x[kIncBatch];
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
+  float v[kIncBatch][5];
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
+    const float *f = flx + (max(x[k], 0) >> 1) * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[k][c] = f[c];
+  }
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) {
+    const float sg = x[k] < 0 ? 0.f : (x[k] & 1) ? -1.f : 1.f;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += sg * (x[k] < 0 ? 0.f : v[k][c]);
+  }
+  for (int t = t0 + kIncBatch; t < t1; ++t) {
+    const int y = inc[t];
+    const float *f = flx + (y >> 1) * 5;
+    const float sg = (y & 1) ? -1.f : 1.f;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += sg * f[c];
+  }
+}
+
+// Adjoint: sum of the u-side (vu) or v-side (vv) per-edge values at local
+// vertex i, in the same order.
+__device__ __forceinline__ void vertex_sum_bwd(const float *vu, const float *vv, const uint16_t *inc,
+                                               const uint16_t *lo, int i, float s[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] = 0.f;
+  const int t0 = lo[i], t1 = lo[i + 1];
+  int x[kIncBatch];
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
+  float v[kIncBatch][5];
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
+    const int y = max(x[k], 0);
+    const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[k][c] = f[c];
+  }
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += x[k] < 0 ? 0.f : v[k][c];
+  }
+  for (int t = t0 + kIncBatch; t < t1; ++t) {
+    const int y = inc[t];
+    const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += f[c];
+  }
+}
+
 // A part's foreign partials (nf rows of 5) to their workspace slots.
 // Part-major workspace (sidx NULL): one contiguous block at the part's slot
 // offset.  Vertex-major: sidx (in LDS) gives each foreign entry's slot, so
@@ -256,33 +322,8 @@ __device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, f
   lds_sync();
 
   for (int i = tid; i < h.U; i += nt) {
-    float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int t0 = lo[i], t1 = lo[i + 1];
-    // the first kIncBatch entries: their indices, then their rows, each as one
-    // batch of LDS reads; the sum still runs in list order
-    int x[kIncBatch];
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
-    float v[kIncBatch][5];
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
-      const float *f = flx + (max(x[k], 0) >> 1) * 5;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) v[k][c] = f[c];
-    }
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) {
-      const float sg = x[k] < 0 ? 0.f : (x[k] & 1) ? -1.f : 1.f;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s[c] += sg * (x[k] < 0 ? 0.f : v[k][c]);
-    }
-    for (int t = t0 + kIncBatch; t < t1; ++t) {
-      const int y = inc[t];
-      const float *f = flx + (y >> 1) * 5;
-      const float sg = (y & 1) ? -1.f : 1.f;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s[c] += sg * f[c];
-    }
+    float s[5];
+    vertex_sum_fwd(flx, inc, lo, i, s);
 #pragma unroll
     for (int c = 0; c < 5; ++c) acc[i * 5 + c] = s[c];
   }
@@ -331,30 +372,8 @@ __device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, f
   lds_sync();
 
   for (int i = tid; i < h.U; i += nt) {
-    float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int t0 = lo[i], t1 = lo[i + 1];
-    int x[kIncBatch];
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
-    float v[kIncBatch][5];
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
-      const int y = max(x[k], 0);
-      const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) v[k][c] = f[c];
-    }
-#pragma unroll
-    for (int k = 0; k < kIncBatch; ++k) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s[c] += x[k] < 0 ? 0.f : v[k][c];
-    }
-    for (int t = t0 + kIncBatch; t < t1; ++t) {
-      const int y = inc[t];
-      const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s[c] += f[c];
-    }
+    float s[5];
+    vertex_sum_bwd(vu, vv, inc, lo, i, s);
 #pragma unroll
     for (int c = 0; c < 5; ++c) gs[i * 5 + c] = s[c];
   }
@@ -436,6 +455,153 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   wait_staged();
   compute_bwd<G, EPT>(h, st, gs, vu, vv, inc, lo, ew, eg, tid, nt);
   write_bwd(h, gs, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
+}
+
+// ---- cache-only kernels: no LDS staging of states
+//
+// The paper's alternative to shared-memory staging relies on the hardware
+// caches alone (its texture-cache variant, Section 5.3): the same parts, task
+// order and packed layout, but each edge reads the states of its endpoints
+// straight from global memory, so repeated vertices of a part hit L1/L2
+// instead of an LDS copy.  Only the foreign ids (to map local to packed
+// vertex ids), the incidence lists and the per-edge values live in LDS; the
+// per-vertex sums, writes and reduction are the staged kernels' own, so the
+// results are bitwise equal.
+
+__device__ __forceinline__ int64_t packed_of(const PartHdr &h, const int32_t *ids, int l) {
+  return l < h.nown ? int64_t(h.own0) + l : int64_t(ids[l - h.nown]);
+}
+
+__device__ __forceinline__ void load_row(const float *__restrict__ src, int64_t v, float out[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) out[c] = src[v * 5 + c];
+}
+
+// LDS: flx[cap][5] | ids[max_nf] | inc[2 cap] u16 | lo[nlo] u16 | sidx[max_nf].
+template <int G, bool QNEW, int EPT>
+__global__ void __launch_bounds__(1024) flux_fwd_cached(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
+                                                        float *__restrict__ qn, float dt, float *__restrict__ ws,
+                                                        int swizzle) {
+  extern __shared__ float smem[];
+  const int part = part_of_block(blockIdx.x, P.k, swizzle);
+  if (part >= P.k) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  float *flx = smem;
+  int32_t *ids = reinterpret_cast<int32_t *>(flx + P.cap * 5);
+  uint16_t *inc = reinterpret_cast<uint16_t *>(ids + P.max_nf);
+  uint16_t *lo = inc + 2 * P.cap;
+  int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
+  const PartHdr h = load_hdr(P, part);
+  stage_ids(P, h, ids, tid, nt);
+  stage_sidx(P, h, sidx, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  wait_staged();
+  float qu[EPT][5], qv[EPT][5];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {  // every row load of the part in one batch; idle lanes read row 0
+    const bool ok = tid + k * nt < h.ne;
+    load_row(q, ok ? packed_of(h, ids, ew[k] & 0xffffu) : 0, qu[k]);
+    load_row(q, ok ? packed_of(h, ids, ew[k] >> 16) : 0, qv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int j = tid + k * nt;
+    if (j < h.ne) {
+      float F[5];
+      edge_flux(qu[k], qv[k], eg[k].x, eg[k].y, eg[k].z, geom_area<G>(eg[k]), F);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) flx[j * 5 + c] = F[c];
+    }
+  }
+  __syncthreads();
+  // per-vertex sums in registers, in the staged kernels' order, then written out
+  float *ro = r + int64_t(h.own0) * 5;
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_fwd(flx, inc, lo, i, s);
+    if (i < h.nown) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        ro[i * 5 + c] = s[c];
+        if constexpr (QNEW) qn[(int64_t(h.own0) + i) * 5 + c] = q[(int64_t(h.own0) + i) * 5 + c] + dt * s[c];
+      }
+    } else {
+      const int f = i - h.nown;
+      const int64_t slot = P.sidx ? int64_t(sidx[f]) : int64_t(h.f0) + f;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) ws[slot * 5 + c] = s[c];
+    }
+  }
+}
+
+// LDS: vu[cap][5] | vv[cap][5] | ids | inc | lo | sidx.
+template <int G, int EPT>
+__global__ void __launch_bounds__(1024) flux_bwd_cached(DevPlan P, const float *__restrict__ q,
+                                                        const float *__restrict__ gr, float *__restrict__ gq,
+                                                        float *__restrict__ ws, int swizzle) {
+  extern __shared__ float smem[];
+  const int part = part_of_block(blockIdx.x, P.k, swizzle);
+  if (part >= P.k) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  float *vu = smem;
+  float *vv = vu + P.cap * 5;
+  int32_t *ids = reinterpret_cast<int32_t *>(vv + P.cap * 5);
+  uint16_t *inc = reinterpret_cast<uint16_t *>(ids + P.max_nf);
+  uint16_t *lo = inc + 2 * P.cap;
+  int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
+  const PartHdr h = load_hdr(P, part);
+  stage_ids(P, h, ids, tid, nt);
+  stage_sidx(P, h, sidx, tid, nt);
+  uint32_t ew[EPT];
+  float4 eg[EPT];
+  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  dma_incidence(inc, lo, P, h, tid, nt);
+  wait_staged();
+  float qu[EPT][5], qv[EPT][5], gu[EPT][5], gv[EPT][5];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {  // idle lanes read row 0
+    const bool ok = tid + k * nt < h.ne;
+    const int64_t pu = ok ? packed_of(h, ids, ew[k] & 0xffffu) : 0, pv = ok ? packed_of(h, ids, ew[k] >> 16) : 0;
+    load_row(q, pu, qu[k]);
+    load_row(q, pv, qv[k]);
+    load_row(gr, pu, gu[k]);
+    load_row(gr, pv, gv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int j = tid + k * nt;
+    if (j < h.ne) {
+      const float hs = 0.5f * kSigma * geom_area<G>(eg[k]);
+      float d[5], ju[5], jv[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) d[c] = gu[k][c] - gv[k][c];
+      euler_vjp(qu[k], eg[k].x, eg[k].y, eg[k].z, d, ju);
+      euler_vjp(qv[k], eg[k].x, eg[k].y, eg[k].z, d, jv);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        vu[j * 5 + c] = 0.5f * ju[c] + hs * d[c];
+        vv[j * 5 + c] = 0.5f * jv[c] - hs * d[c];
+      }
+    }
+  }
+  __syncthreads();
+  float *go = gq + int64_t(h.own0) * 5;
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_bwd(vu, vv, inc, lo, i, s);
+    if (i < h.nown) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) go[i * 5 + c] = s[c];
+    } else {
+      const int f = i - h.nown;
+      const int64_t slot = P.sidx ? int64_t(sidx[f]) : int64_t(h.f0) + f;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) ws[slot * 5 + c] = s[c];
+    }
+  }
 }
 
 // ---- pipelined persistent kernels
@@ -859,6 +1025,37 @@ hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q,
     EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<4, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
   } else {
     EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<2, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_cached(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
+                              float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s) {
+  if (P.k == 0) return hipSuccess;
+  const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
+  const int ept = edges_per_thread(P.cap, wg);
+  if (backward) {
+    if (P.geom_ncomp == 4) {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_cached<4, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
+    } else {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_cached<2, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
+    }
+  } else if (P.geom_ncomp == 4) {
+    if (qn) {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<4, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+                                             swizzle))
+    } else {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<4, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+                                             swizzle))
+    }
+  } else {
+    if (qn) {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<2, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+                                             swizzle))
+    } else {
+      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<2, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+                                             swizzle))
+    }
   }
   return hipGetLastError();
 }

@@ -51,6 +51,13 @@ int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool
                     2 * (4 * cap + 2 * nlo);
   return (b + 15) & ~int64_t(15);
 }
+// Mirror of the cache-only kernels' LDS: per-edge values (two arrays for the
+// adjoint), foreign ids, incidence lists and offsets, slot indices.
+int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd) {
+  const int64_t nlo = (max_u + 3) & ~int64_t(1);
+  const int64_t b = 4 * (bwd ? 10 : 5) * cap + 4 * max_nf + 2 * (2 * cap + nlo) + 4 * max_nf;
+  return (b + 15) & ~int64_t(15);
+}
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
   const int64_t b = 4 * (max_ux + 2 * max_uy) + 8 * (wg / 64);
   return (b + 15) & ~int64_t(15);
@@ -399,6 +406,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->lds_pipe_fwd = flux_pipe_lds(P->max_u, P->max_nf, cap, false, false);
       P->lds_pipe_fwd_qn = flux_pipe_lds(P->max_u, P->max_nf, cap, false, true);
       P->lds_pipe_bwd = flux_pipe_lds(P->max_u, P->max_nf, cap, true, false);
+      P->lds_cached_fwd = flux_cached_lds(P->max_u, P->max_nf, cap, false);
+      P->lds_cached_bwd = flux_cached_lds(P->max_u, P->max_nf, cap, true);
       const int64_t G = gstore, na = P->n_active_out;
       const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
@@ -498,7 +507,7 @@ int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
   epk::clear_error();
   if (!p || !info) return epk::fail(EPK_EINVAL, "NULL argument");
   const int64_t bf = epk::plan_bytes(p, 0), bb = epk::plan_bytes(p, 1), br = epk::plan_bytes(p, 2);
-  const int64_t v[15] = {p->k,
+  const int64_t v[16] = {p->k,
                          p->lds_fwd,
                          p->lds_bwd,
                          p->wg,
@@ -512,8 +521,9 @@ int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
                          p->pipe ? p->grid_pipe_fwd : 0,
                          p->pipe ? p->grid_pipe_bwd : 0,
                          p->lds_pipe_bwd,
-                         p->vmajor ? 1 : 0};
-  for (int32_t i = 0; i < n_info && i < 15; ++i) info[i] = v[i];
+                         p->vmajor ? 1 : 0,
+                         p->staging};
+  for (int32_t i = 0; i < n_info && i < 16; ++i) info[i] = v[i];
   return EPK_OK;
 }
 
@@ -532,6 +542,18 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   }
   if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
   p->pipe = 0;  // the pipelined grid depends on both: set it again
+  return EPK_OK;
+}
+
+int epk_plan_set_staging(epk_plan *p, int32_t staged) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (staged != 0 && staged != 1) return epk::fail(EPK_EINVAL, "staged must be 0 or 1");
+  if (p->kind != EPK_FLUX5) return epk::fail(EPK_EINVAL, "the cache-only kernels are for FLUX5 plans");
+  if (!staged && (p->lds_cached_fwd > epk::kMaxLdsBytes || p->lds_cached_bwd > epk::kMaxLdsBytes))
+    return epk::fail(EPK_ERANGE, "capacity needs more LDS than a workgroup may use");
+  p->staging = staged;
+  if (!staged) p->pipe = 0;  // the pipelined launch stages states
   return EPK_OK;
 }
 

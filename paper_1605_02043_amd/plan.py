@@ -96,11 +96,11 @@ class Plan:
         return st.as_dict()
 
     def info(self) -> dict:
-        a = np.zeros(15, dtype=np.int64)
-        check(lib.epk_plan_info(self._h, i64p(a), 15))
+        a = np.zeros(16, dtype=np.int64)
+        check(lib.epk_plan_info(self._h, i64p(a), 16))
         keys = ["n_parts", "lds_fwd", "lds_bwd", "wg", "ncls", "bytes_fwd", "bytes_bwd", "bytes_fwd_kernel",
                 "bytes_bwd_kernel", "max_nf", "pipe", "grid_pipe_fwd", "grid_pipe_bwd", "lds_pipe_bwd",
-                "vertex_major"]
+                "vertex_major", "staging"]
         return dict(zip(keys, a.tolist()))
 
     def perm(self) -> np.ndarray:
@@ -134,6 +134,10 @@ class Plan:
     def set_launch(self, wg: int = 0, xcd_swizzle: int = -1):
         """Workgroup size and XCD-aware part mapping; switches the pipelined launch off."""
         check(lib.epk_plan_set_launch(self._h, int(wg), int(xcd_swizzle)))
+
+    def set_staging(self, staged: int = 1):
+        """FLUX5: stage states in LDS (1) or read them through the caches only (0)."""
+        check(lib.epk_plan_set_staging(self._h, int(staged)))
 
     def set_slot_layout(self, layout: int = -1):
         """Workspace layout of the replicated partials: 0 part-major, 1 vertex-major, -1 automatic."""
