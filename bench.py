@@ -76,6 +76,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--no-baselines", action="store_true", help="skip the random and greedy vertex-cut orders")
+    ap.add_argument("--adaptive", type=int, default=0, metavar="STEPS",
+                    help="run STEPS forward steps under adaptive overhead control (background partition) and exit")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -310,6 +312,8 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, torch)
         return
+    if args.adaptive:
+        return bench_adaptive(args, torch)
     if args.workload == "rmat20":
         return bench_spmv(args, torch)
     if args.workload == "batch256":
@@ -416,6 +420,46 @@ def main():
         out["dram_counters"] = "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a 1 GiB copy"
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(G, args.cpu_budget_s)
+    print(json.dumps(out), flush=True)
+
+
+def bench_adaptive(args, torch):
+    """Time to run a fixed number of forward steps when the partition is built in the
+    background (the default order runs meanwhile), against waiting for it first."""
+    import gen
+    from paper_1605_02043_amd.adaptive import AdaptiveFlux
+
+    G = gen.workload(args.workload, seed=0)
+    m = len(G["edges"])
+    q0 = gen.flux_state(G["n"], seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ad = AdaptiveFlux(G["edges"], G["n"], args.cap, G["geom"].astype(np.float32))
+    q = ad.pack(q0)
+    switched_at = None
+    for i in range(args.adaptive):
+        if ad.decision is None and i % 64 == 0:
+            q = ad.maybe_switch(q)
+            if ad.decision is not None:
+                switched_at = i
+        ad.forward(q)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = ad.bg.poll()
+    t = ad.timings
+    out = _common(args, "edges/s over a fixed run of forward steps, partition built in the background", 
+                  args.adaptive * m / wall, wall * 1e3 / args.adaptive,
+                  {"workload": f"{args.workload}: {args.adaptive} forward steps under adaptive overhead control",
+                   "capacity": args.cap})
+    est = {}
+    if t:
+        est = {"default_only_s": args.adaptive * t["input_ms"] * 1e-3,
+               "partition_first_s": info["seconds"] + args.adaptive * t["ep_ms"] * 1e-3}
+    out["adaptive"] = {"decision": ad.decision, "switched_at_step": switched_at, "wall_s": wall,
+                       "partition_and_plan_s": info["seconds"], "saving_bound": info["saving_bound"],
+                       "step_ms": t, "estimates": est}
+    out["cpu_baseline"] = None
+    ad.close()
     print(json.dumps(out), flush=True)
 
 

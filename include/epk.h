@@ -47,7 +47,8 @@ typedef enum {
   EPK_ERANGE = -2, /* sizes beyond what the kernels support (LDS budget, 16-bit local ids) */
   EPK_EHIP = -3,   /* HIP runtime or launch error */
   EPK_ESTATE = -4, /* plan/batch not uploaded, or used with the wrong kind */
-  EPK_ENOMEM = -5  /* host allocation failed */
+  EPK_ENOMEM = -5, /* host allocation failed */
+  EPK_ECANCELED = -6 /* a background partition was cancelled */
 } epk_status;
 
 typedef enum {
@@ -214,6 +215,30 @@ int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in,
  * rows of ncomp float32; packs states into / out of packed order.         */
 int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp,
                      int32_t inverse, void *stream);
+
+/* -------------------------------------------------------------- adaptive */
+
+/* Adaptive overhead control (the paper's EP-adapt, Sections 4.2 and 5): the
+ * edge partition and plan are built on a background CPU thread while the
+ * caller keeps running its default order; the caller polls, takes the plan
+ * when it is ready and keeps whichever order times faster.  A reuse
+ * pre-check runs first: every order loads at least n_active vertex copies,
+ * so 1 - n_active / L_input (L_input: the default order's loads at this
+ * capacity) bounds the fraction of loads any partition can save; below
+ * min_saving the partition is skipped.  The graph arrays are copied; the
+ * handle owns its thread.  Host only.                                     */
+typedef struct epk_adaptive epk_adaptive;
+int epk_adaptive_start(const epk_graph *g, int32_t capacity, int32_t kind, double min_saving, epk_adaptive **out);
+/* state: 0 running, 1 plan ready, 2 skipped by the pre-check, 3 failed or
+ * cancelled; saving_bound: the pre-check's bound; seconds: partition + plan
+ * time once finished.  Any output pointer may be NULL.                    */
+int epk_adaptive_poll(epk_adaptive *a, int32_t *state, double *saving_bound, double *seconds);
+/* Hand over the EP plan (the caller destroys it); wait = 1 blocks until the
+ * thread finishes.  EPK_ESTATE while running, after a skip or once taken.  */
+int epk_adaptive_take(epk_adaptive *a, int32_t wait, epk_plan **plan);
+/* Cancel an unfinished partition (it stops at its next coarsening level or
+ * refinement pass, returning EPK_ECANCELED inside), join, free.           */
+void epk_adaptive_destroy(epk_adaptive *a);
 
 /* --------------------------------------------------------------- batched */
 

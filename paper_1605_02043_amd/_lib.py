@@ -8,7 +8,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libepk.so")
 
-EPK_OK, EPK_EINVAL, EPK_ERANGE, EPK_EHIP, EPK_ESTATE, EPK_ENOMEM = 0, -1, -2, -3, -4, -5
+EPK_OK, EPK_EINVAL, EPK_ERANGE, EPK_EHIP, EPK_ESTATE, EPK_ENOMEM, EPK_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 ORDER = {"ep": 0, "input": 1, "ggp": 2, "random": 3, "greedy": 4}
 KIND = {"flux5": 0, "spmv": 1}
 
@@ -75,6 +75,10 @@ _SIGS = {
     "epk_batch_destroy": (None, [_P]),
     "epk_autotune": (C.c_int, [C.POINTER(Graph), C.c_int32, _I32P, C.c_int32, C.c_char_p, _P, C.c_size_t, _P,
                                _I32P, _I32P]),
+    "epk_adaptive_start": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_double, C.POINTER(_P)]),
+    "epk_adaptive_poll": (C.c_int, [_P, _I32P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "epk_adaptive_take": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
+    "epk_adaptive_destroy": (None, [_P]),
     "epk_last_error": (C.c_char_p, []),
     "epk_version": (C.c_char_p, []),
 }

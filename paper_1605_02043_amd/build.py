@@ -20,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["partition.cpp", "multilevel.cpp", "baselines.cpp", "plan.cpp"]
+HOST_SOURCES = ["partition.cpp", "multilevel.cpp", "baselines.cpp", "plan.cpp", "adaptive.cpp"]
 HIP_SOURCES = ["kernels.hip", "api.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]

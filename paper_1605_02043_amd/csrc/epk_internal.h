@@ -1,6 +1,7 @@
 // Internal declarations shared by the host (C++) and device (HIP) parts of libepk.
 #pragma once
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -18,6 +19,13 @@ constexpr int kHeavyBlock = 256;
 
 int fail(int status, const std::string &msg);
 void clear_error();
+
+// Cooperative cancellation of a partition running on a background thread: the
+// thread sets its flag with set_cancel_flag; the partitioner calls
+// check_cancel at its level and pass boundaries, which throws Cancelled.
+struct Cancelled {};
+void set_cancel_flag(const std::atomic<bool> *flag);
+void check_cancel();
 
 // ------------------------------------------------------------ partitioner
 

@@ -213,6 +213,7 @@ void refine(const LGraph &G, std::vector<int32_t> &part, int32_t k, int32_t cap)
   std::vector<int32_t> cl;
   std::vector<char> in(size_t(k), 0);
   for (int pass = 0; pass < 8; ++pass) {
+    check_cancel();
     int64_t moved = 0;
     for (int32_t u = 0; u < n; ++u) {
       const int32_t a = part[u];
@@ -349,6 +350,7 @@ void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::ve
   std::vector<std::vector<int32_t>> cmaps;
   levels.push_back(finest(m, nbr));
   while (int64_t(levels.back().n) > 16 * int64_t(k)) {
+    check_cancel();
     std::vector<int32_t> cmap;
     LGraph C = coarsen(levels.back(), maxw, cmap);
     if (10 * int64_t(C.n) > 9 * int64_t(levels.back().n)) break;

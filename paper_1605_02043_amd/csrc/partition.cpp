@@ -205,6 +205,12 @@ void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const s
   st.balance = (m && k) ? double(max_pe) / (double(m) / double(k)) : 0.0;
 }
 
+static thread_local const std::atomic<bool> *tl_cancel = nullptr;
+void set_cancel_flag(const std::atomic<bool> *flag) { tl_cancel = flag; }
+void check_cancel() {
+  if (tl_cancel && tl_cancel->load(std::memory_order_relaxed)) throw Cancelled{};
+}
+
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
   if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
@@ -238,6 +244,8 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
     if (inc_out) *inc_out = std::move(inc);
   } catch (const std::bad_alloc &) {
     return fail(EPK_ENOMEM, "host allocation failed while partitioning");
+  } catch (const Cancelled &) {
+    return fail(EPK_ECANCELED, "partition cancelled");
   }
   return EPK_OK;
 }

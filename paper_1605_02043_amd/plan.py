@@ -82,6 +82,15 @@ class Plan:
         self.workspace = None
         self.device = None
 
+    @classmethod
+    def _adopt(cls, handle, n: int, m: int, cap: int, kind: str = "flux5", n_x: int = 0):
+        """Wrap a plan built elsewhere in the library (the adaptive handle); takes ownership."""
+        self = cls.__new__(cls)
+        self.kind, self.n, self.n_x, self.m, self.cap = kind, int(n), int(n_x), int(m), int(cap)
+        self._h = handle
+        self.image = self.workspace = self.device = None
+        return self
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

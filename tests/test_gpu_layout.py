@@ -140,3 +140,29 @@ def test_cache_only_edge_cases_against_oracle():
         assert_close(f"cache-only/{name}/q_new", unpack_rows(qn.cpu().numpy(), perm), qref, qA)
         assert_close(f"cache-only/{name}/g_q", unpack_rows(g.cpu().numpy(), perm), flux.backward(nv, E, g64, q, gr),
                      flux.backward_abs(nv, E, g64, q, gr))
+
+
+def test_adaptive_flux_switches_and_matches_oracle():
+    """Default order first, the partitioned plan once its background build finishes; the
+    state follows the switch and the results stay those of the oracle."""
+    import time
+
+    from oracle import flux
+    from paper_1605_02043_amd.adaptive import AdaptiveFlux
+
+    G = gen.workload("tet32", seed=1)
+    q0 = gen.flux_state(G["n"], seed=1)
+    ad = AdaptiveFlux(G["edges"], G["n"], 256, G["geom"].astype(np.float32), min_saving=0.05)
+    q = ad.pack(q0)
+    t0 = time.perf_counter()
+    while ad.decision is None and time.perf_counter() - t0 < 60:
+        q = ad.maybe_switch(q)
+        ad.forward(q)
+    torch.cuda.synchronize()
+    say(f"case adaptive decision={ad.decision} timings={ad.timings}")
+    assert ad.decision in ("ep", "input")
+    r = ad.unpack(ad.forward(q))
+    g64 = G["geom"].astype(np.float32).astype(np.float64)
+    assert_close("adaptive/r", r, flux.forward(G["n"], G["edges"], g64, q0), flux.forward_abs(G["n"], G["edges"], g64, q0))
+    assert np.array_equal(ad.unpack(q), q0.astype(np.float32))
+    ad.close()
