@@ -523,13 +523,25 @@ def bench_spmv(args, torch):
                                "reduce": float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))},
                 "algorithmic_bytes": {"spmv": info["bytes_fwd_kernel"],
                                       "reduce": info["bytes_fwd"] - info["bytes_fwd_kernel"]}}
+        # the adjoint (g_x = A^T g_y) on the same plan
+        gy = torch.ones(R["n_y"], dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup):
+            P.spmv_adjoint(gy)
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(args.steps):
+            P.spmv_adjoint(gy)
+        a1.record()
+        torch.cuda.synchronize()
+        adj_ms = a0.elapsed_time(a1) / args.steps
         st = P.stats
         auto = layouts["vertex_major" if auto_layout else "part_major"]
         best = min(layouts.values(), key=lambda v: v["ms_per_step"])
         # the partitioned order runs its automatic layout; the baselines are quoted at their best one
         use = auto if name == "ep" else best
         res[name] = dict(use, layout="vertex_major" if use is layouts.get("vertex_major") else "part_major",
-                         layouts=layouts, loads_per_edge=st["loads"] / m, slots_per_edge=st["slots"] / m,
+                         layouts=layouts, adjoint_ms=adj_ms, adjoint_edges_per_s=m / (adj_ms * 1e-3),
+                         loads_per_edge=st["loads"] / m, slots_per_edge=st["slots"] / m,
                          plan_seconds=plan_s, partition_seconds=st["partition_seconds"])
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
         del P

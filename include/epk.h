@@ -208,6 +208,17 @@ int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stre
 int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                   float dt, float *q_new, void *d_ws, void *stream);
 /* op codes of epk_run_stage */
+/* SpMV adjoint on the same plan: g_x = A^T g_y (g_x[j] = sum over the
+ * nonzeros (i, j) of w g_y[i]) and, if g_w != NULL, the weight gradient
+ * g_w[e] = g_y[i] x[j] for every edge e in ORIGINAL edge order.  x: packed
+ * [n_x] (only read for g_w; may be NULL otherwise), g_y: packed [n - n_x],
+ * g_x: packed [n_x], g_w: [m]; d_ws as for epk_spmv (the adjoint's x-class
+ * partials share it, so do not overlap it with a forward on the same
+ * workspace).  Two launches: the part kernel (per-part incidence lists over
+ * x, fixed ascending order) and the x-class reduction (ascending part
+ * order).                                                                 */
+int epk_spmv_adjoint(const epk_plan *p, const float *x, const float *g_y, float *g_x, float *g_w, void *d_ws,
+                     void *stream);
 #define EPK_OP_FORWARD 0
 #define EPK_OP_BACKWARD 1
 #define EPK_OP_SPMV 2

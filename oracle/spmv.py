@@ -31,3 +31,22 @@ def row(n_x: int, edges: np.ndarray, w: np.ndarray, x: np.ndarray, i: int):
     sel = edges[:, 1] == n_x + i
     t = np.asarray(w, np.float64)[sel] * np.asarray(x, np.float64)[edges[sel, 0]]
     return float(t.sum()), float(np.abs(t).sum())
+
+
+def backward(n_x: int, n_y: int, edges: np.ndarray, w: np.ndarray, x: np.ndarray, g_y: np.ndarray):
+    """Adjoint of y = A x: g_x = A^T g_y (g_x[j] = sum over edges (j, i) of w g_y[i]) and the
+    weight gradient g_w[e] = g_y[i] x[j], both in FP64."""
+    edges = np.asarray(edges, dtype=np.int64)
+    j = edges[:, 0]
+    i = edges[:, 1] - n_x
+    w64 = np.asarray(w, np.float64)
+    gy = np.asarray(g_y, np.float64)
+    g_x = np.bincount(j, weights=w64 * gy[i], minlength=n_x)
+    g_w = gy[i] * np.asarray(x, np.float64)[j]
+    return g_x, g_w
+
+
+def backward_abs(n_x: int, n_y: int, edges: np.ndarray, w: np.ndarray, x: np.ndarray, g_y: np.ndarray):
+    """The same sums over absolute values (the rounding-error scale of each output)."""
+    return backward(n_x, n_y, edges, np.abs(np.asarray(w, np.float64)), np.abs(np.asarray(x, np.float64)),
+                    np.abs(np.asarray(g_y, np.float64)))

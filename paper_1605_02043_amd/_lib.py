@@ -63,6 +63,7 @@ _SIGS = {
     "epk_forward": (C.c_int, [_P, _FP, _FP, C.c_float, _FP, _P, _P]),
     "epk_backward": (C.c_int, [_P, _FP, _FP, _FP, _P, _P]),
     "epk_spmv": (C.c_int, [_P, _FP, _FP, _P, _P]),
+    "epk_spmv_adjoint": (C.c_int, [_P, _FP, _FP, _FP, _FP, _P, _P]),
     "epk_run_stage": (C.c_int, [_P, C.c_int32, C.c_int32, _FP, _FP, _FP, C.c_float, _FP, _P, _P]),
     "epk_permute_rows": (C.c_int, [_FP, _FP, _P, C.c_int64, C.c_int32, C.c_int32, _P]),
     "epk_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P)]),

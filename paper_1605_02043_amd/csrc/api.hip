@@ -39,6 +39,14 @@ DevPlan dev_plan(const epk_plan *p) {
   P.rslot = p->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = nullptr;
+  if (p->kind == EPK_SPMV) {
+    P.xinc = dptr<uint16_t>(b, L.xinc);
+    P.xlo = dptr<uint16_t>(b, L.xlo);
+    P.xlofs = dptr<int32_t>(b, L.xlofs);
+    P.rfid = dptr<int32_t>(b, L.rfid);
+    P.eid = dptr<int32_t>(b, L.eid);
+    P.xsidx = p->xvmajor ? dptr<int32_t>(b, L.xsidx) : nullptr;
+  }
   P.m = p->m;
   P.k = int32_t(p->k);
   P.cap = p->cap;
@@ -51,6 +59,22 @@ DevPlan dev_plan(const epk_plan *p) {
   P.max_uy = int32_t(p->max_uy);
   P.max_nf = int32_t(p->max_nf);
   P.n_iso = 0;
+  return P;
+}
+
+DevPlan dev_plan_xreduce(const epk_plan *p) {
+  DevPlan P = dev_plan(p);
+  void *b = p->d_image;
+  const ImageLayout &L = p->lay;
+  P.rvid = dptr<int32_t>(b, L.xrvid);
+  P.roff = dptr<int32_t>(b, L.xroff);
+  P.sidx = p->xvmajor ? dptr<int32_t>(b, L.xsidx) : nullptr;
+  P.rslot = p->xvmajor ? nullptr : dptr<int32_t>(b, L.xrslot);
+  P.heavy = dptr<int32_t>(b, L.xheavy);
+  P.R = int32_t(p->xR);
+  P.n_heavy = int32_t(p->xn_heavy);
+  P.n = p->n_x;
+  P.n_active = int32_t(p->xn_active);
   return P;
 }
 
@@ -415,6 +439,24 @@ int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q
 int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream) {
   clear_error();
   return run_stage(p, EPK_OP_SPMV, -1, x, nullptr, y, 0.f, nullptr, d_ws, stream);
+}
+
+int epk_spmv_adjoint(const epk_plan *p, const float *x, const float *g_y, float *g_x, float *g_w, void *d_ws,
+                     void *stream) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (p->kind != EPK_SPMV) return fail(EPK_ESTATE, "not an SpMV plan");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  if ((p->n_x > 0 && !g_x) || (p->n_out > 0 && !g_y)) return fail(EPK_EINVAL, "g_x or g_y is NULL");
+  if (g_w && !x && p->n_x > 0) return fail(EPK_EINVAL, "g_w needs x");
+  if (p->xn_slots > 0 && !d_ws) return fail(EPK_EINVAL, "workspace is NULL");
+  if (p->lds_bwd > kMaxLdsBytes) return fail(EPK_ERANGE, "parts too large for the adjoint's LDS");
+  const DevPlan P = dev_plan(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float *ws = static_cast<float *>(d_ws);
+  hipError_t e = launch_spmv_adjoint(P, p->wg, size_t(p->lds_bwd), x, g_y, g_x, g_w, ws, p->swizzle, s);
+  if (e != hipSuccess) return hip_status(e, "adjoint kernel launch");
+  return hip_status(launch_reduce(dev_plan_xreduce(p), 1, g_x, ws, nullptr, nullptr, 0.f, s), "reduce launch");
 }
 
 int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp, int32_t inverse,

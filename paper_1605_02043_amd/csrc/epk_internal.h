@@ -60,6 +60,8 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
   size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
+  // SpMV adjoint: x incidence per part, y foreign ids, x-class reduction tables
+  size_t xinc = 0, xlo = 0, xlofs = 0, rfid = 0, eid = 0, xrvid = 0, xroff = 0, xsidx = 0, xrslot = 0, xheavy = 0;
   size_t total = 0;
 };
 
@@ -77,6 +79,12 @@ struct DevPlan {
   const int32_t *rslot;  // part-major workspace: the slots of each replicated vertex (else NULL)
   const int32_t *heavy;
   const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
+  const uint16_t *xinc;  // SpMV adjoint: kernel-order edges of each local x, per part
+  const uint16_t *xlo;   // SpMV adjoint: list offsets (part's block at xlofs[part])
+  const int32_t *xlofs;
+  const int32_t *rfid;   // SpMV adjoint: packed ids (y numbering) of each part's foreign y
+  const int32_t *eid;    // SpMV adjoint: original edge id of each kernel-order edge
+  const int32_t *xsidx;  // SpMV adjoint: x slot of each foreign x (vertex-major x workspace, else NULL)
   const int32_t *eoff;   // [k + 1] first task of every part
   int64_t m;
   int32_t k;
@@ -119,6 +127,9 @@ struct epk_plan {
   int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
   int64_t n_slots = 0;  // foreign entries of the reduced class = workspace rows
   bool vmajor = false;  // workspace layout: vertex-major (true) or part-major
+  // SpMV adjoint's x-class reduction
+  int64_t xR = 0, xn_heavy = 0, xn_active = 0, xn_slots = 0;
+  bool xvmajor = false;
   void *d_image = nullptr;
 };
 
@@ -143,8 +154,10 @@ int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap);
 int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew);
 int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd);
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
+int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
 DevPlan dev_plan(const epk_plan *p);
+DevPlan dev_plan_xreduce(const epk_plan *p);  // the SpMV adjoint's x-class reduction
 DevPlan dev_batch(const epk_batch *b);
 }  // namespace epk

@@ -18,6 +18,8 @@ hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, cons
                             float *out, float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s);
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
                        hipStream_t s);
+hipError_t launch_spmv_adjoint(const DevPlan &P, int wg, size_t lds, const float *x, const float *gy, float *gx,
+                               float *gw, float *ws, int swizzle, hipStream_t s);
 hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, const float *q, float *qn, float dt,
                          hipStream_t s);
 hipError_t launch_permute(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int ncomp, int inverse,

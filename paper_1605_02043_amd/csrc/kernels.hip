@@ -872,6 +872,78 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
   }
 }
 
+// SpMV adjoint over the same parts (Section 5.2's graph, gradients flowing
+// back): g_x = A^T g_y, i.e. g_x[j] = sum over the edges (j, i) of w g_y[i],
+// and, if g_w is not NULL, the weight gradient g_w[e] = g_y[i] x[j] in
+// original edge order.  The part's y gradients (owned block, then foreign y by
+// id) and, for g_w, its x values are staged in LDS like the forward's x; each
+// local x sums its edges' values over a per-part incidence list in ascending
+// kernel order; owned x are written directly, foreign x partials go to the
+// workspace and an x-class reduction adds them in ascending part order.
+// LDS: gys[max_uy] | xs[max_ux] | val[cap] | xinc[cap, even] u16 | xlo[nlo] u16 | xsl[max_ux].
+__global__ void __launch_bounds__(1024) spmv_adj_kernel(DevPlan P, const float *__restrict__ x,
+                                                        const float *__restrict__ gy, float *__restrict__ gx,
+                                                        float *__restrict__ gw, float *__restrict__ ws, int swizzle) {
+  extern __shared__ float smem[];
+  const int part = part_of_block(blockIdx.x, P.k, swizzle);
+  if (part >= P.k) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
+  const int4 ha = h4[0], hb = h4[1];
+  const int xo = ha.x, xn = ha.y, xf0 = ha.z, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
+  const int64_t e0 = P.eoff[part];
+  const int ne = int(P.eoff[part + 1] - e0);
+  const int ux = xn + xnf;
+  float *gys = smem;
+  float *xs = gys + P.max_uy;
+  float *val = xs + P.max_u;
+  uint16_t *xinc = reinterpret_cast<uint16_t *>(val + P.cap);
+  uint16_t *xlo = xinc + ((P.cap + 1) & ~1);
+  int32_t *xsl = reinterpret_cast<int32_t *>(xlo + ((P.max_u + 3) & ~1));
+  const int lane = tid & 63;
+
+  // batch 1: owned blocks, foreign ids (into the slots their values take), edges, x incidence
+  int32_t *yid = reinterpret_cast<int32_t *>(gys + yn);
+  dma_block(gys, gy + yo, yn, tid, nt);
+  dma_block(reinterpret_cast<float *>(yid), reinterpret_cast<const float *>(P.rfid + yf0), ynf, tid, nt);
+  int32_t *xid = reinterpret_cast<int32_t *>(xs + xn);
+  if (gw) {
+    dma_block(xs, x + xo, xn, tid, nt);
+    dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.fid + xf0), xnf, tid, nt);
+  }
+  if (P.xsidx) dma_block(reinterpret_cast<float *>(xsl), reinterpret_cast<const float *>(P.xsidx + xf0), xnf, tid, nt);
+  dma_block(reinterpret_cast<float *>(xinc), reinterpret_cast<const float *>(P.xinc) + e0, (ne + 1) >> 1, tid, nt);
+  dma_block(reinterpret_cast<float *>(xlo), reinterpret_cast<const float *>(P.xlo + P.xlofs[part]), (ux + 2) >> 1, tid,
+            nt);
+  const bool valid = tid < ne;
+  const int64_t ec = clamp_edge(P, int(e0), ne, tid);
+  const uint32_t w = P.eloc[ec];
+  const float wt = P.geom[ec];
+  const int32_t oe = gw ? P.eid[ec] : 0;
+  wait_staged();
+  // batch 2: foreign values, each lane overwriting the id it read
+  for (int d = tid; d < ynf; d += nt) __builtin_amdgcn_global_load_lds(gy + yid[d], EPK_LDS(gys + yn + (d - lane)), 4, 0, 0);
+  if (gw)
+    for (int d = tid; d < xnf; d += nt) __builtin_amdgcn_global_load_lds(x + xid[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
+  wait_staged();
+
+  if (valid) {
+    const float g = gys[w >> 16];
+    val[tid] = wt * g;
+    if (gw) gw[oe] = g * xs[w & 0xffffu];
+  }
+  __syncthreads();
+  for (int i = tid; i < ux; i += nt) {
+    float s = 0.0f;
+    const int t1 = xlo[i + 1];
+    for (int t = xlo[i]; t < t1; ++t) s += val[xinc[t]];
+    if (i < xn)
+      gx[xo + i] = s;
+    else
+      ws[P.xsidx ? int64_t(xsl[i - xn]) : int64_t(xf0) + (i - xn)] = s;
+  }
+}
+
 // ------------------------------------------------------------------ reduction
 
 // Light vertices (<= kHeavySlots partials): one thread per vertex,
@@ -1097,6 +1169,14 @@ hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, flo
                        hipStream_t s) {
   if (P.k == 0) return hipSuccess;
   hipLaunchKernelGGL(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_adjoint(const DevPlan &P, int wg, size_t lds, const float *x, const float *gy, float *gx,
+                               float *gw, float *ws, int swizzle, hipStream_t s) {
+  if (P.k == 0) return hipSuccess;
+  hipLaunchKernelGGL(spmv_adj_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, gy, gx, gw, ws,
+                     swizzle);
   return hipGetLastError();
 }
 

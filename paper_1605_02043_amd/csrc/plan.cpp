@@ -58,6 +58,13 @@ int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd) {
   const int64_t b = 4 * (bwd ? 10 : 5) * cap + 4 * max_nf + 2 * (2 * cap + nlo) + 4 * max_nf;
   return (b + 15) & ~int64_t(15);
 }
+// SpMV adjoint: y gradients, x values, per-edge values, x incidence lists and
+// offsets, x slot indices.
+int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap) {
+  const int64_t nlo = (max_ux + 3) & ~int64_t(1), ncap = (cap + 1) & ~int64_t(1);
+  const int64_t b = 4 * (max_uy + max_ux + cap) + 2 * (ncap + nlo) + 4 * max_ux;
+  return (b + 15) & ~int64_t(15);
+}
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
   const int64_t b = 4 * (max_ux + 2 * max_uy) + 8 * (wg / 64);
   return (b + 15) & ~int64_t(15);
@@ -209,6 +216,15 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::vector<int32_t> fl[2];
     std::vector<int32_t> cnt, cur;
     std::vector<int64_t> order_idx;
+    // SpMV adjoint: per part, the kernel-order edges of each local x (ascending)
+    std::vector<uint16_t> xinc, xlo;
+    std::vector<int32_t> xlofs;
+    std::vector<int32_t> eid;  // SpMV adjoint: original edge id of each kernel-order edge
+    if (kind == EPK_SPMV) {
+      xinc.resize(size_t(2 * m));  // a part's list starts at 2 e0, an even index
+      xlofs.reserve(size_t(k));
+      eid.resize(size_t(m));
+    }
     int64_t lofs = 0;
     int64_t fdev = 0;           // running x/all foreign offset in fid
     int64_t fred = 0;           // running foreign offset of the reduced class (slot base)
@@ -305,6 +321,17 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
           const int32_t e = P->task[pos + j];
           eloc[e0 + jj] = lx[j] | (ly[j] << 16);
           geomk[size_t(e0 + jj)] = g->edge_geom[size_t(e)];
+          eid[e0 + jj] = e;
+        }
+        {
+          const int32_t Ux = nown[0] + nf[0];
+          std::vector<int32_t> c(size_t(Ux) + 1, 0);
+          for (int64_t jj = 0; jj < ne; ++jj) c[(eloc[e0 + jj] & 0xffffu) + 1]++;
+          for (int32_t i = 0; i < Ux; ++i) c[i + 1] += c[i];
+          xlofs.push_back(int32_t(xlo.size()));
+          for (int32_t i = 0; i <= Ux; ++i) xlo.push_back(uint16_t(c[i]));
+          if ((Ux + 1) & 1) xlo.push_back(0);  // lists start at even indices: staged as whole dwords
+          for (int64_t jj = 0; jj < ne; ++jj) xinc[2 * e0 + c[eloc[e0 + jj] & 0xffffu]++] = uint16_t(jj);
         }
         h[0] = own0[0];
         h[1] = nown[0];
@@ -357,6 +384,32 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->n_out = nred;
     P->n_active_out = kind == EPK_SPMV ? active[1] - P->n_x : active[0];
 
+    // ---- SpMV adjoint: the same tables for the x class (its foreign entries are fid)
+    std::vector<int32_t> xrvid, xroff(1, 0), xsidx, xrslot, xheavy;
+    if (kind == EPK_SPMV) {
+      std::vector<int32_t> xc(size_t(P->n_x), 0), xs(size_t(P->n_x), 0);
+      for (int32_t v : fid) xc[v]++;
+      for (int32_t v = 0; v < P->n_x; ++v) {
+        if (xc[v] == 0) continue;
+        xs[v] = xroff.back();
+        if (xc[v] > kHeavySlots) xheavy.push_back(int32_t(xrvid.size()));
+        xrvid.push_back(v);
+        xroff.push_back(xroff.back() + xc[v]);
+      }
+      std::fill(xc.begin(), xc.end(), 0);
+      xsidx.resize(fid.size());
+      xrslot.resize(fid.size());
+      for (size_t q = 0; q < fid.size(); ++q) {
+        xsidx[q] = xs[fid[q]] + xc[fid[q]]++;
+        xrslot[xsidx[q]] = int32_t(q);
+      }
+      P->xR = int64_t(xrvid.size());
+      P->xn_heavy = int64_t(xheavy.size());
+      P->xn_active = active[0];
+      P->xn_slots = int64_t(fid.size());
+      P->xvmajor = P->xn_slots > 4 * P->xR;
+    }
+
     // ---- device image
     ImageLayout &L = P->lay;
     size_t off = 0;
@@ -377,6 +430,16 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.roff = take(roff.size() * 4);
     L.sidx = take(sidx.size() * 4);
     L.rslot = take(rslot.size() * 4);
+    L.xinc = take(xinc.size() * 2);
+    L.xlo = take(xlo.size() * 2);
+    L.xlofs = take(xlofs.size() * 4);
+    L.rfid = take(kind == EPK_SPMV ? red_foreign.size() * 4 : 0);
+    L.eid = take(eid.size() * 4);
+    L.xrvid = take(xrvid.size() * 4);
+    L.xroff = take(xroff.size() * 4);
+    L.xsidx = take(xsidx.size() * 4);
+    L.xrslot = take(xrslot.size() * 4);
+    L.xheavy = take(xheavy.size() * 4);
     L.heavy = take(heavy.size() * 4);
     L.total = std::max<size_t>(off, 256);
     P->image.assign(L.total, 0);
@@ -392,9 +455,22 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     put(P->image, L.roff, roff);
     put(P->image, L.sidx, sidx);
     put(P->image, L.rslot, rslot);
+    if (kind == EPK_SPMV) {
+      put(P->image, L.xinc, xinc);
+      put(P->image, L.xlo, xlo);
+      put(P->image, L.xlofs, xlofs);
+      put(P->image, L.rfid, red_foreign);
+      put(P->image, L.eid, eid);
+      put(P->image, L.xrvid, xrvid);
+      put(P->image, L.xroff, xroff);
+      put(P->image, L.xsidx, xsidx);
+      put(P->image, L.xrslot, xrslot);
+      put(P->image, L.xheavy, xheavy);
+    }
     put(P->image, L.heavy, heavy);
     const int nc = kind == EPK_SPMV ? 1 : 5;
-    P->ws_bytes = align256(std::max<size_t>(red_foreign.size() * nc * 4, 4));
+    // the SpMV adjoint's x partials share the workspace (one launch pair at a time)
+    P->ws_bytes = align256(std::max<size_t>(std::max(red_foreign.size() * nc, size_t(P->xn_slots)) * 4, 4));
 
     // ---- LDS and algorithmic bytes
     const int64_t C = P->stats.cost, Lds = P->stats.loads, R = P->R;
@@ -415,7 +491,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->bytes_reduce = 4 * R + 4 * (R + 1) + 20 * Cred + 40 * R + 20 * (nred - na);
       P->bytes_reduce_qnew = P->bytes_reduce + 40 * R + 40 * (nred - na);
     } else {
-      P->lds_fwd = P->lds_bwd = spmv_lds(P->max_u, P->max_uy, P->wg);
+      P->lds_fwd = spmv_lds(P->max_u, P->max_uy, P->wg);
+      P->lds_bwd = spmv_adj_lds(P->max_u, P->max_uy, cap);
       // x loads = owned x + foreign x over all parts
       int64_t Lxs = 0, Cx = 0;
       for (int64_t p = 0; p < k; ++p) {
@@ -538,7 +615,7 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   if (xcd_swizzle < -1 || xcd_swizzle > 1) return epk::fail(EPK_EINVAL, "xcd_swizzle must be -1, 0 or 1");
   if (wg != 0) {
     p->wg = wg;
-    if (p->kind == EPK_SPMV) p->lds_fwd = p->lds_bwd = epk::spmv_lds(p->max_u, p->max_uy, wg);
+    if (p->kind == EPK_SPMV) p->lds_fwd = epk::spmv_lds(p->max_u, p->max_uy, wg);
   }
   if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
   p->pipe = 0;  // the pipelined grid depends on both: set it again

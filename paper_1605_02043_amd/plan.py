@@ -211,6 +211,20 @@ class Plan:
         check(lib.epk_spmv(self._h, _dptr(x), _dptr(y), _dptr(self.workspace), _stream_handle(torch, self.device)))
         return y
 
+    def spmv_adjoint(self, g_y, x=None, weights_grad: bool = False):
+        """g_x = A^T g_y (packed x order) and, with weights_grad, g_w[e] = g_y[i] x[j] in
+        original edge order (x, packed, is then required)."""
+        import torch
+
+        self._check_state(g_y, self.n - self.n_x, 1, "g_y")
+        if weights_grad:
+            self._check_state(x, self.n_x, 1, "x")
+        g_x = torch.empty(self.n_x, dtype=torch.float32, device=self.device)
+        g_w = torch.empty(self.m, dtype=torch.float32, device=self.device) if weights_grad else None
+        check(lib.epk_spmv_adjoint(self._h, _dptr(x if weights_grad else None), _dptr(g_y), _dptr(g_x), _dptr(g_w),
+                                   _dptr(self.workspace), _stream_handle(torch, self.device)))
+        return (g_x, g_w) if weights_grad else g_x
+
     # ---------------------------------------------------------------- packing
     def pack(self, state_orig, perm_dev=None):
         """Rows of state_orig (original vertex order) -> packed order."""

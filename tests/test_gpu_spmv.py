@@ -85,3 +85,29 @@ def test_spmv_hub_row_and_determinism():
         y2, _ = _run(g, 128, order, x)
         assert np.array_equal(y1, y2)
         assert_close(f"spmv-hub/{order}", y1, ref, A)
+
+
+@pytest.mark.parametrize("order,cap", [("ep", 256), ("input", 256), ("ep", 64), ("ep", 1024)])
+def test_spmv_adjoint_against_oracle(order, cap):
+    """g_x = A^T g_y and the weight gradient, through the C ABI, against the FP64 oracle."""
+    from paper_1605_02043_amd import Plan
+
+    R = gen.rmat(scale=14, n_edges=1 << 18, seed=5)
+    g = spmv_graph(R, R["shuffle"])
+    say(f"case spmv adjoint order={order} cap={cap}")
+    P = Plan(g["edges"], g["n"], cap, g["w"], order=order, kind="spmv", n_x=g["n_x"]).upload("cuda")
+    perm = P.perm()
+    n_x = g["n_x"]
+    rng = np.random.default_rng(1)
+    gy = rng.standard_normal(R["n_y"]).astype(np.float32)
+    xp = torch.from_numpy(np.ascontiguousarray(R["x"][perm[:n_x]])).cuda()
+    gyp = torch.from_numpy(np.ascontiguousarray(gy[perm[n_x:] - n_x])).cuda()
+    g_x, g_w = P.spmv_adjoint(gyp, xp, weights_grad=True)
+    torch.cuda.synchronize()
+    gx = np.empty(n_x, dtype=np.float32)
+    gx[perm[:n_x]] = g_x.cpu().numpy()
+    ref_x, ref_w = spmv.backward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)
+    abs_x, abs_w = spmv.backward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)
+    assert_close(f"spmv-adj/{order}/{cap}/g_x", gx, ref_x, abs_x)
+    assert_close(f"spmv-adj/{order}/{cap}/g_w", g_w.cpu().numpy(), ref_w, abs_w)
+    assert torch.equal(P.spmv_adjoint(gyp), g_x)  # without the weight gradient: the same g_x, bit for bit

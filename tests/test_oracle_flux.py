@@ -222,3 +222,34 @@ def test_spmv_matches_scipy_with_duplicates():
     yi, ai = spmv.row(R["n_x"], g["edges"], g["w"], R["x"], i)
     assert abs(yi - y[i]) <= 1e-12 * ai
     assert (spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"]) >= np.abs(y) - 1e-12).all()
+
+
+def test_spmv_adjoint_matches_scipy_transpose_and_dot_product():
+    """g_x = A^T g_y against scipy's transpose product (duplicates summed); <A x, g> = <x, A^T g>;
+    the weight gradient against central differences of <g_y, A(w) x> (linear in w, so exact up to
+    rounding)."""
+    from gen.rmat import spmv_graph
+
+    R = gen.rmat(scale=9, n_edges=3000, seed=4)
+    g = spmv_graph(R)
+    n_x, n_y = R["n_x"], R["n_y"]
+    j = g["edges"][:, 0]
+    i = g["edges"][:, 1] - n_x
+    w = g["w"].astype(np.float64)
+    A = sp.coo_matrix((w, (i, j)), shape=(n_y, n_x)).tocsr()
+    rng = np.random.default_rng(0)
+    gy = rng.standard_normal(n_y)
+    x = R["x"].astype(np.float64)
+    g_x, g_w = spmv.backward(n_x, n_y, g["edges"], g["w"], x, gy)
+    assert np.allclose(g_x, A.T @ gy, rtol=1e-12, atol=1e-12)
+    y = spmv.forward(n_x, n_y, g["edges"], g["w"], x)
+    assert abs(y @ gy - x @ g_x) <= 1e-10 * (np.abs(y) @ np.abs(gy) + 1)
+    for e in rng.choice(len(w), 25, replace=False):
+        h = 1e-3
+        wp, wm = w.copy(), w.copy()
+        wp[e] += h
+        wm[e] -= h
+        fd = (spmv.forward(n_x, n_y, g["edges"], wp, x) @ gy - spmv.forward(n_x, n_y, g["edges"], wm, x) @ gy) / (2 * h)
+        assert abs(fd - g_w[e]) <= 1e-8 * (1 + abs(g_w[e]))
+    ax, aw = spmv.backward_abs(n_x, n_y, g["edges"], g["w"], x, gy)
+    assert (ax >= np.abs(g_x) - 1e-12).all() and (aw >= np.abs(g_w) - 1e-12).all()
