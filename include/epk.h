@@ -62,7 +62,7 @@ typedef enum {
   /* single-pass greedy growing on the same transform: k = ceil(m / cap),
    * parts 0..k-2 hold exactly cap edges, tasks in placement order */
   EPK_ORDER_GGP = 2,
-  /* baselines from the paper's related work (PowerGraph's vertex cuts), same
+  /* baselines of Section 3.3's comparison (PowerGraph's vertex cuts), same
    * k = ceil(m / cap) and capacity: random placement (edges sorted by the
    * SplitMix64 hash of their id, consecutive blocks of cap) and greedy
    * placement (edges in id order onto the least loaded part already holding
@@ -178,7 +178,7 @@ int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
 int epk_plan_set_slot_layout(epk_plan *p, int32_t layout);
 /* FLUX5 only: staged = 1 (default) stages each part's vertex states in LDS,
  * one fetch per distinct vertex (Section 4); staged = 0 runs the paper's
- * cache-only alternative (Section 5.3's texture-cache variant): the same
+ * cache-only alternative (Section 5.2's texture-cache variant): the same
  * parts, task order and packed layout, each edge reading its endpoints'
  * states from global memory through L1/L2.  Bitwise the same results.
  * Switches the pipelined launch off.  EPK_ERANGE if its LDS does not fit. */

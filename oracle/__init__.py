@@ -22,7 +22,7 @@ GPU Caching Problems"):
                 formula; the formula here is this project's reading).
 * ``spmv``    - y_i += w * x_j over the bipartite SpMV graph (Section 5.2).
 * ``baselines`` - PowerGraph's random and greedy vertex-cut placements, the
-                partitioners the paper's related work quotes (Section 3).
+                partitioners the paper compares against (Section 3.3).
 * ``brute``   - exhaustive optimal partitions for tiny graphs (Theorems 1-2).
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned

@@ -1,4 +1,4 @@
-"""Edge-partition baselines from the paper's related work (Section 3): the
+"""Edge-partition baselines the paper compares against (Section 3.3): the
 vertex-cut placements of PowerGraph (Gonzalez et al., OSDI 2012), random and
 greedy, under the same hard capacity as the other orders: k = ceil(m/cap)
 parts of at most cap edges.

@@ -1,5 +1,6 @@
-// Edge-partition baselines quoted by the paper (Section 3, related work):
-// the vertex-cut placements of PowerGraph (Gonzalez et al., OSDI 2012), random
+// Edge-partition baselines the paper compares against (Section 3.3, other
+// edge partition methods): the vertex-cut placements of PowerGraph (Gonzalez
+// et al., OSDI 2012), random
 // and greedy, here with the same hard capacity as the other orders
 // (k = ceil(m / cap) parts of at most cap edges).
 //

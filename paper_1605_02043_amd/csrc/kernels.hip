@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
 // ---- cache-only kernels: no LDS staging of states
 //
 // The paper's alternative to shared-memory staging relies on the hardware
-// caches alone (its texture-cache variant, Section 5.3): the same parts, task
+// caches alone (its texture-cache variant, Section 5.2): the same parts, task
 // order and packed layout, but each edge reads the states of its endpoints
 // straight from global memory, so repeated vertices of a part hit L1/L2
 // instead of an LDS copy.  Only the foreign ids (to map local to packed
