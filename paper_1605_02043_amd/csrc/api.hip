@@ -33,6 +33,7 @@ DevPlan dev_plan(const epk_plan *p) {
   P.inc = dptr<uint16_t>(b, L.inc);
   P.loff = dptr<uint16_t>(b, L.loff);
   P.fid = dptr<int32_t>(b, L.fid);
+  P.pfid = p->kind == EPK_FLUX5 ? dptr<int32_t>(b, L.pfid) : nullptr;
   P.rvid = dptr<int32_t>(b, L.rvid);
   P.roff = dptr<int32_t>(b, L.roff);
   P.sidx = p->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;
@@ -47,7 +48,7 @@ DevPlan dev_plan(const epk_plan *p) {
     P.eid = dptr<int32_t>(b, L.eid);
     P.xsidx = p->xvmajor ? dptr<int32_t>(b, L.xsidx) : nullptr;
   }
-  P.m = p->m;
+  P.m = p->me;
   P.k = int32_t(p->k);
   P.cap = p->cap;
   P.geom_ncomp = p->geom_ncomp;
@@ -95,7 +96,7 @@ DevPlan dev_batch(const epk_batch *bt) {
   P.rslot = bt->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = dptr<int32_t>(b, L.iso);
-  P.m = bt->m;
+  P.m = bt->me;
   P.k = int32_t(bt->k);
   P.cap = int32_t(bt->max_cap);
   P.geom_ncomp = 4;
@@ -165,9 +166,9 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
       hdr.push_back(int32_t(hq[6] + lofs_off));
       hdr.push_back(hq[7]);
     }
-    eloc.insert(eloc.end(), hptr<uint32_t>(p, L.eloc), hptr<uint32_t>(p, L.eloc) + p->m);
-    geom.insert(geom.end(), hptr<float>(p, L.geom), hptr<float>(p, L.geom) + 3 * p->m);
-    inc.insert(inc.end(), hptr<uint16_t>(p, L.inc), hptr<uint16_t>(p, L.inc) + 2 * p->m);
+    eloc.insert(eloc.end(), hptr<uint32_t>(p, L.eloc), hptr<uint32_t>(p, L.eloc) + p->me);
+    geom.insert(geom.end(), hptr<float>(p, L.geom), hptr<float>(p, L.geom) + 3 * p->me);
+    inc.insert(inc.end(), hptr<uint16_t>(p, L.inc), hptr<uint16_t>(p, L.inc) + 2 * p->me);
     loff.insert(loff.end(), hptr<uint16_t>(p, L.loff), hptr<uint16_t>(p, L.loff) + nloff);
     for (int64_t i = 0; i < C; ++i) fid.push_back(int32_t(hptr<int32_t>(p, L.fid)[i] + voff));
     for (int64_t i = 0; i < p->R; ++i) {
@@ -187,19 +188,20 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     // the slot tables are read once per launch pair, by the part kernel or the reduction
     B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce + 4 * p->n_slots;
     B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce + 4 * p->n_slots;
-    eoff += p->m;
+    eoff += p->me;
+    B->m += p->m;
     foff += C;
     lofs_off += nloff;
     rbase += p->R;
     B->k += p->k;
   }
-  B->m = eoff;
+  B->me = eoff;
   B->n = B->voff[n_graphs];
   B->R = rbase;
   B->vmajor = int64_t(sidx.size()) > 4 * B->R;
   B->n_heavy = int64_t(heavy.size());
   B->n_iso = int64_t(iso.size());
-  if (B->k >= (int64_t(1) << 31) || B->n >= (int64_t(1) << 31) || B->m >= (int64_t(1) << 31)) {
+  if (B->k >= (int64_t(1) << 31) || B->n >= (int64_t(1) << 31) || B->me >= (int64_t(1) << 31)) {
     delete B;
     return fail(EPK_ERANGE, "batch too large for 32-bit ids");
   }

@@ -58,7 +58,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
-  size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0;
+  size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0, pfid = 0;
   size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
   // SpMV adjoint: x incidence per part, y foreign ids, x-class reduction tables
   size_t xinc = 0, xlo = 0, xlofs = 0, rfid = 0, eid = 0, xrvid = 0, xroff = 0, xsidx = 0, xrslot = 0, xheavy = 0;
@@ -73,6 +73,7 @@ struct DevPlan {
   const uint16_t *inc;
   const uint16_t *loff;
   const int32_t *fid;
+  const int32_t *pfid;   // FLUX5 plan: foreign ids again, part p's at p * max_nf (else NULL)
   const int32_t *rvid;
   const int32_t *roff;
   const int32_t *sidx;   // vertex-major workspace: slot of each foreign entry (else NULL)
@@ -86,7 +87,7 @@ struct DevPlan {
   const int32_t *eid;    // SpMV adjoint: original edge id of each kernel-order edge
   const int32_t *xsidx;  // SpMV adjoint: x slot of each foreign x (vertex-major x workspace, else NULL)
   const int32_t *eoff;   // [k + 1] first task of every part
-  int64_t m;
+  int64_t m;          // edge records in the image (FLUX5 plan: k * cap, part p's from p * cap)
   int32_t k;
   int32_t cap;
   int32_t geom_ncomp;
@@ -105,6 +106,7 @@ struct DevPlan {
 struct epk_plan {
   int32_t n = 0, n_x = 0, kind = 0, order = 0, cap = 0, geom_ncomp = 0, ncls = 1, wg = 256, swizzle = 1;
   int64_t m = 0, k = 0;
+  int64_t me = 0;  // edge records in the image: FLUX5 k * cap (part p's edges from p * cap), SpMV m
   std::vector<int32_t> part, task, perm;
   std::vector<int32_t> own_begin, own_count;  // [k * ncls]
   std::vector<int64_t> foreign_off;           // [k * ncls + 1]
@@ -137,6 +139,7 @@ struct epk_batch {
   int32_t n_graphs = 0;
   std::vector<int64_t> voff;  // [n_graphs + 1]
   int64_t m = 0, k = 0, n = 0;
+  int64_t me = 0;  // edge records in the merged image
   std::vector<uint8_t> image;
   epk::ImageLayout lay;
   size_t ws_bytes = 0;

@@ -36,6 +36,10 @@ int grid_of_parts(int k, int swizzle) { return swizzle ? 8 * ((k + 7) / 8) : k; 
 
 // ------------------------------------------------------------------ FLUX5
 
+// 1 / x by the hardware reciprocal (within 1 ulp): one instruction where an
+// IEEE division takes about ten, and the kernels are bound by instruction issue.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Edge flux a * F(q_u, q_v, n) of the cfd-style interaction, evaluated from
 // the area vector A = a n: the Euler normal flux is linear in the normal, so
 // a f(q, n) = f(q, A), and only the dissipation term needs a = |A| itself.
@@ -47,10 +51,11 @@ __device__ __forceinline__ void edge_flux(const float *qu, const float *qv, floa
     const float *q = w ? qv : qu;
     float *f = w ? fv : fu;
     const float rho = q[0], m1 = q[1], m2 = q[2], m3 = q[3], E = q[4];
+    const float ir = rcp(rho);
     const float mn = m1 * n1 + m2 * n2 + m3 * n3;
     const float mm = m1 * m1 + m2 * m2 + m3 * m3;
-    const float s = mn / rho;
-    const float p = kG1 * (E - 0.5f * mm / rho);
+    const float s = mn * ir;
+    const float p = kG1 * (E - 0.5f * mm * ir);
     f[0] = mn;  // rho * s
     f[1] = m1 * s + p * n1;
     f[2] = m2 * s + p * n2;
@@ -68,7 +73,7 @@ __device__ __forceinline__ void edge_flux(const float *qu, const float *qv, floa
 __device__ __forceinline__ void euler_vjp(const float *q, float n1, float n2, float n3, const float d[5],
                                           float out[5]) {
   const float rho = q[0], m1 = q[1], m2 = q[2], m3 = q[3], E = q[4];
-  const float ir = 1.0f / rho;
+  const float ir = rcp(rho);
   const float mn = m1 * n1 + m2 * n2 + m3 * n3;
   const float mm = m1 * m1 + m2 * m2 + m3 * m3;
   const float s = mn * ir;
@@ -95,12 +100,13 @@ __device__ __forceinline__ float4 load_geom(const float *geom, int64_t e) {
   }
 }
 
-// The face area: |A| in 3D, 1 in 2D.  Evaluated once the loads have landed,
-// so that no arithmetic sits between a load and the next one.
+// The face area: |A| in 3D (hardware square root, within 1 ulp), 1 in 2D.
+// Evaluated once the loads have landed, so that no arithmetic sits between a
+// load and the next one.
 template <int G>
 __device__ __forceinline__ float geom_area(const float4 &g) {
   if constexpr (G == 4)
-    return sqrtf(g.x * g.x + g.y * g.y + g.z * g.z);
+    return __builtin_amdgcn_sqrtf(g.x * g.x + g.y * g.y + g.z * g.z);
   else
     return 1.0f;
 }
@@ -151,6 +157,21 @@ __device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\
 
 constexpr int kIncBatch = 4;  // incidence entries per vertex read as one batch (mesh degrees are <= 4)
 
+// The first kIncBatch incidence entries of the list [t0, t1) and a mask per
+// entry (all ones inside the list, zero past its end), read as one batch
+// whatever the list length.  The empty asm hides the masks from the compiler,
+// which would otherwise turn each masked use into a branch.
+__device__ __forceinline__ void inc_batch(const uint16_t *inc, int t0, int t1, int y[kIncBatch],
+                                          int in[kIncBatch]) {
+  static_assert(kIncBatch == 4, "one asm operand per entry");
+#pragma unroll
+  for (int k = 0; k < kIncBatch; ++k) {
+    y[k] = inc[t0 + k];
+    in[k] = -int(t0 + k < t1);
+  }
+  asm volatile("" : "+v"(in[0]), "+v"(in[1]), "+v"(in[2]), "+v"(in[3]));
+}
+
 struct PartHdr {
   int e0, ne, own0, nown, f0, nf, lofs, U;
 };
@@ -159,6 +180,20 @@ __device__ __forceinline__ PartHdr load_hdr(const DevPlan &P, int part) {
   const int4 *h = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
   const int4 a = h[0], b = h[1];
   return {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+// Header of a part as one dword per lane (lane l holds field l mod 8); zero
+// for a part past the end.  Read into scalars (hdr_unpack) only after the
+// wait for the load, so that the load itself never waits.
+__device__ __forceinline__ int hdr_lanes(const DevPlan &P, int part) {
+  if (part < 0) return 0;
+  return P.hdr[int64_t(part) * kHdrInts + (threadIdx.x & 7)];
+}
+
+__device__ __forceinline__ PartHdr hdr_unpack(int v) {
+  return {__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1), __builtin_amdgcn_readlane(v, 2),
+          __builtin_amdgcn_readlane(v, 3), __builtin_amdgcn_readlane(v, 4), __builtin_amdgcn_readlane(v, 5),
+          __builtin_amdgcn_readlane(v, 6), __builtin_amdgcn_readlane(v, 7)};
 }
 
 // Incidence entries (2 u16 per edge, one dword) and offsets (U + 1 u16 from an
@@ -190,6 +225,20 @@ __device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, i
   }
 }
 
+// Edge records of a single plan's part from its fixed block [e0, e0 + cap):
+// every lane reads a record (past ne, zero padding it never uses), so the
+// loads need no header.
+template <int G, int EPT>
+__device__ __forceinline__ void load_edge_block(const DevPlan &P, int64_t e0, int tid, int nt, uint32_t ew[EPT],
+                                                float4 eg[EPT]) {
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int64_t e = e0 + min(tid + k * nt, P.cap - 1);
+    ew[k] = P.eloc[e];
+    eg[k] = load_geom<G>(P.geom, e);
+  }
+}
+
 // ------------------------------------------------------------------ FLUX5 parts
 //
 // A part goes through three dependent loads and a compute stage:
@@ -198,8 +247,10 @@ __device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, i
 //   B  owned rows and foreign rows (by id) into an LDS state buffer, the local
 //      incidence lists and offsets into LDS, edge data into registers;
 //   C  flux from LDS, per-vertex sums in a fixed order, the writes.
-// The direct kernels run one part per workgroup and wait after each load
-// stage.  The pipelined kernels run a fixed grid that overlaps the stages of
+// The direct kernels run one part per workgroup.  A single plan keeps a
+// part's edge records at p cap and its foreign ids at p max_nf, so H, A and
+// the edge data are issued together; B's rows follow after one wait.  The
+// pipelined kernels run a fixed grid that overlaps the stages of
 // consecutive parts of one workgroup (see flux_*_pipe).
 
 __device__ __forceinline__ void stage_ids(const DevPlan &P, const PartHdr &h, int32_t *ids, int tid, int nt) {
@@ -218,31 +269,37 @@ __device__ __forceinline__ void stage_state(const PartHdr &h, const float *__res
 // their rows, each as one batch of LDS reads.
 __device__ __forceinline__ void vertex_sum_fwd(const float *flx, const uint16_t *inc, const uint16_t *lo, int i,
                                                float s[5]) {
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] = 0.f;
   const int t0 = lo[i], t1 = lo[i + 1];
-  // the first kIncBatch entries: their indices, then their rows, each as one
-  // batch of LDS reads; the sum still runs in list order
-  int x[kIncBatch];
-#pragma unroll
-  for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
-  float v[kIncBatch][5];
-#pragma unroll
-  for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
-    const float *f = flx + (max(x[k], 0) >> 1) * 5;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) v[k][c] = f[c];
-  }
+  // the first kIncBatch entries, then their rows, each as one batch of LDS
+  // reads and with no branch.  An entry past the list (the next vertex's, or
+  // padding) gets weight 0 and reads row 0 (a finite flux); the sum still runs
+  // in list order.
+  int y[kIncBatch], in[kIncBatch], x[kIncBatch];
+  float w[kIncBatch];
+  inc_batch(inc, t0, t1, y, in);
 #pragma unroll
   for (int k = 0; k < kIncBatch; ++k) {
-    const float sg = x[k] < 0 ? 0.f : (x[k] & 1) ? -1.f : 1.f;
+    x[k] = ((y[k] >> 1) * 5) & in[k];
+    // +1 or -1 by the side bit (the sign bit of the float), 0 past the list
+    w[k] = __int_as_float((0x3f800000 | ((y[k] & 1) << 31)) & in[k]);
+  }
+  float v[kIncBatch][5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) s[c] += sg * (x[k] < 0 ? 0.f : v[k][c]);
+  for (int k = 0; k < kIncBatch; ++k) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[k][c] = flx[x[k] + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] = w[0] * v[0][c];
+#pragma unroll
+  for (int k = 1; k < kIncBatch; ++k) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += w[k] * v[k][c];
   }
   for (int t = t0 + kIncBatch; t < t1; ++t) {
-    const int y = inc[t];
-    const float *f = flx + (y >> 1) * 5;
-    const float sg = (y & 1) ? -1.f : 1.f;
+    const int e = inc[t];
+    const float *f = flx + (e >> 1) * 5;
+    const float sg = (e & 1) ? -1.f : 1.f;
 #pragma unroll
     for (int c = 0; c < 5; ++c) s[c] += sg * f[c];
   }
@@ -252,30 +309,34 @@ __device__ __forceinline__ void vertex_sum_fwd(const float *flx, const uint16_t 
 // vertex i, in the same order.
 __device__ __forceinline__ void vertex_sum_bwd(const float *vu, const float *vv, const uint16_t *inc,
                                                const uint16_t *lo, int i, float s[5]) {
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] = 0.f;
   const int t0 = lo[i], t1 = lo[i + 1];
-  int x[kIncBatch];
+  const int dv = int(vv - vu);  // the v-side rows, as an offset from vu
+  int y[kIncBatch], in[kIncBatch], x[kIncBatch];
+  float w[kIncBatch];
+  inc_batch(inc, t0, t1, y, in);
 #pragma unroll
-  for (int k = 0; k < kIncBatch; ++k) x[k] = t0 + k < t1 ? int(inc[t0 + k]) : -1;
-  float v[kIncBatch][5];
-#pragma unroll
-  for (int k = 0; k < kIncBatch; ++k) {  // unused slots read row 0 and add zero
-    const int y = max(x[k], 0);
-    const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) v[k][c] = f[c];
+  for (int k = 0; k < kIncBatch; ++k) {  // as in vertex_sum_fwd: past the list, weight 0 on row 0
+    x[k] = ((y[k] >> 1) * 5 + (y[k] & 1) * dv) & in[k];
+    w[k] = __int_as_float(0x3f800000 & in[k]);
   }
+  float v[kIncBatch][5];
 #pragma unroll
   for (int k = 0; k < kIncBatch; ++k) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) s[c] += x[k] < 0 ? 0.f : v[k][c];
+    for (int c = 0; c < 5; ++c) v[k][c] = vu[x[k] + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] = w[0] * v[0][c];
+#pragma unroll
+  for (int k = 1; k < kIncBatch; ++k) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += w[k] * v[k][c];
   }
   for (int t = t0 + kIncBatch; t < t1; ++t) {
-    const int y = inc[t];
-    const float *f = ((y & 1) ? vv : vu) + (y >> 1) * 5;
+    const int e = inc[t];
+    const float *g = vu + (e >> 1) * 5 + (e & 1) * dv;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) s[c] += f[c];
+    for (int c = 0; c < 5; ++c) s[c] += g[c];
   }
 }
 
@@ -407,15 +468,19 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   uint16_t *lo = inc + 2 * P.cap;
   int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
   int32_t *ids = reinterpret_cast<int32_t *>(flx);
-  const PartHdr h = load_hdr(P, part);
-  stage_ids(P, h, ids, tid, nt);
-  stage_sidx(P, h, sidx, tid, nt);
+  // foreign ids, edge records and header: none waits for another
+  dma_block(reinterpret_cast<float *>(ids), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
+            P.max_nf, tid, nt);
   uint32_t ew[EPT];
   float4 eg[EPT];
-  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  load_edge_block<G, EPT>(P, int64_t(part) * P.cap, tid, nt, ew, eg);
+  const int hv = hdr_lanes(P, part);
+  wait_staged();
+  const PartHdr h = hdr_unpack(hv);
+  // owned and foreign rows, incidence lists and offsets, slot indices
+  stage_sidx(P, h, sidx, tid, nt);
   dma_incidence(inc, lo, P, h, tid, nt);
   dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  wait_staged();
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   wait_staged();
   compute_fwd<G, EPT>(h, st, acc, flx, inc, lo, ew, eg, tid, nt);
@@ -440,16 +505,18 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   uint16_t *lo = inc + 2 * P.cap;
   int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
   int32_t *ids = reinterpret_cast<int32_t *>(vu);
-  const PartHdr h = load_hdr(P, part);
-  stage_ids(P, h, ids, tid, nt);
-  stage_sidx(P, h, sidx, tid, nt);
+  dma_block(reinterpret_cast<float *>(ids), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
+            P.max_nf, tid, nt);
   uint32_t ew[EPT];
   float4 eg[EPT];
-  load_edges<G, EPT>(P, h, tid, nt, ew, eg);
+  load_edge_block<G, EPT>(P, int64_t(part) * P.cap, tid, nt, ew, eg);
+  const int hv = hdr_lanes(P, part);
+  wait_staged();
+  const PartHdr h = hdr_unpack(hv);
+  stage_sidx(P, h, sidx, tid, nt);
   dma_incidence(inc, lo, P, h, tid, nt);
   dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
   dma_block(gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  wait_staged();
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   dma_rows<5>(gs + h.nown * 5, gr, ids, h.nf, tid, nt);
   wait_staged();
@@ -630,19 +697,6 @@ __device__ __forceinline__ int pipe_part(int k, int t, int swizzle) {
   }
   const int part = b + t * G;
   return part < k ? part : -1;
-}
-
-// Header of a part as one dword per lane (lane l holds field l mod 8); zero
-// for a part past the end.  Read into scalars only after the loop's wait.
-__device__ __forceinline__ int hdr_lanes(const DevPlan &P, int part) {
-  if (part < 0) return 0;
-  return P.hdr[int64_t(part) * kHdrInts + (threadIdx.x & 7)];
-}
-
-__device__ __forceinline__ PartHdr hdr_unpack(int v) {
-  return {__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1), __builtin_amdgcn_readlane(v, 2),
-          __builtin_amdgcn_readlane(v, 3), __builtin_amdgcn_readlane(v, 4), __builtin_amdgcn_readlane(v, 5),
-          __builtin_amdgcn_readlane(v, 6), __builtin_amdgcn_readlane(v, 7)};
 }
 
 // LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):

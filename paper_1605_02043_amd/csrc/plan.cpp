@@ -199,14 +199,19 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->foreign_ids.clear();
     P->foreign_ids.reserve(size_t(P->stats.cost));
     std::vector<int32_t> stamp(size_t(n), -1), loc(size_t(n), 0);
-    std::vector<uint32_t> eloc(static_cast<size_t>(m));
+    // FLUX5 edge records sit at a fixed stride: part p's at [p cap, p cap + ne),
+    // the rest of its block zero.  A kernel then knows where a part's edges are
+    // before its header has arrived.  SpMV records are contiguous.
+    const int64_t me = kind == EPK_FLUX5 ? k * int64_t(cap) : m;
+    P->me = me;
+    std::vector<uint32_t> eloc(static_cast<size_t>(me));
     // 3D flux geometry (n, a) is stored as the area vector A = a n: 3 floats per edge
     const int gstore = (kind == EPK_FLUX5 && g->geom_ncomp == 4) ? 3 : g->geom_ncomp;
-    std::vector<float> geomk(size_t(m) * size_t(gstore));
+    std::vector<float> geomk(size_t(me) * size_t(gstore));
     std::vector<int32_t> hdr(size_t(k) * kHdrInts, 0);
     std::vector<uint16_t> incl, loff;
     if (kind == EPK_FLUX5) {
-      incl.resize(size_t(2 * m));
+      incl.resize(size_t(2 * me));
       loff.reserve(size_t(P->stats.loads + k));
     }
     std::vector<int32_t> fid;  // device foreign-id list (FLUX5: all; SpMV: x only)
@@ -268,6 +273,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       };
       int32_t *h = &hdr[size_t(p) * kHdrInts];
       if (kind == EPK_FLUX5) {
+        const int64_t e0 = p * int64_t(cap);  // the part's record block
         const int32_t U = nown[0] + nf[0];
         cnt.assign(size_t(U) + 1, 0);
         for (int64_t j = 0; j < ne; ++j) {
@@ -351,6 +357,16 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->max_u = max_u[0];
     P->max_uy = max_u[1];
     P->max_nf = max_nf;
+    // FLUX5: every part's foreign ids again, in a block of max_nf at p max_nf
+    // (padding -1 is never used), so a part's ids are found from its index alone
+    std::vector<int32_t> pfid;
+    if (kind == EPK_FLUX5) {
+      pfid.assign(size_t(k * max_nf), -1);
+      for (int64_t p = 0; p < k; ++p) {
+        const int32_t *h = &hdr[size_t(p) * kHdrInts];
+        std::copy(fid.begin() + h[4], fid.begin() + h[4] + h[5], pfid.begin() + p * max_nf);
+      }
+    }
 
     // ---- reduction tables: for each replicated vertex of the reduced class,
     // its slots (non-owner parts) in ascending part order.  Two workspace
@@ -426,6 +442,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.inc = take(incl.size() * 2);
     L.loff = take(loff.size() * 2);
     L.fid = take(fid.size() * 4);
+    L.pfid = take(pfid.size() * 4);
     L.rvid = take(rvid.size() * 4);
     L.roff = take(roff.size() * 4);
     L.sidx = take(sidx.size() * 4);
@@ -451,6 +468,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     put(P->image, L.loff, loff);
     P->n_loff = int64_t(loff.size());
     put(P->image, L.fid, fid);
+    put(P->image, L.pfid, pfid);
     put(P->image, L.rvid, rvid);
     put(P->image, L.roff, roff);
     put(P->image, L.sidx, sidx);
