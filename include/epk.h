@@ -174,14 +174,17 @@ int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
  * when the reduced class has more than four partials per replicated vertex,
  * as around power-law hubs).  The sum order, ascending part id, and hence
  * every result bit, is the same under both.  Host only; takes effect at the
- * next launch.                                                            */
+ * next launch.  The vertex-major layout also stages each part's slot
+ * indices in LDS: EPK_ERANGE (layout unchanged) if they no longer fit.   */
 int epk_plan_set_slot_layout(epk_plan *p, int32_t layout);
 /* FLUX5 only: staged = 1 (default) stages each part's vertex states in LDS,
  * one fetch per distinct vertex (Section 4); staged = 0 runs the paper's
  * cache-only alternative (Section 5.2's texture-cache variant): the same
  * parts, task order and packed layout, each edge reading its endpoints'
- * states from global memory through L1/L2.  Bitwise the same results.
- * Switches the pipelined launch off.  EPK_ERANGE if its LDS does not fit. */
+ * states from global memory through L1/L2.  The same results up to
+ * rounding: the kernels are compiled separately, and the compiler may fuse
+ * a multiply and an add differently.  Switches the pipelined launch off.
+ * EPK_ERANGE if its LDS does not fit.                                     */
 int epk_plan_set_staging(epk_plan *p, int32_t staged);
 void epk_plan_destroy(epk_plan *p);
 

@@ -219,8 +219,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     hdr.swap(sorted);
   }
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
-  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false);
-  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false);
+  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false, B->vmajor);
+  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false, B->vmajor);
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");

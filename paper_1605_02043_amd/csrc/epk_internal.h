@@ -152,10 +152,12 @@ struct epk_batch {
 
 namespace epk {
 // LDS bytes of the FLUX5 kernels for a given part shape (must match the kernels' carve-up).
-int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool qnew);
-int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap);
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew);
-int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd);
+// sidx: the vertex-major workspace's slot indices take LDS too.
+int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
+int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx);
+int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
+void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its current layout
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);

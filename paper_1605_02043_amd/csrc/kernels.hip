@@ -115,32 +115,39 @@ __device__ __forceinline__ float geom_area(const float4 &g) {
 
 #define EPK_LDS(p) ((__attribute__((address_space(3))) void *)(p))
 
-// Copy src[0, n) to LDS dst[0, n) with direct-to-LDS loads: lane l of a wave
-// writes its dword at (wave base + 4 l); the base d - lane is wave-uniform
-// because the block size is a multiple of 64.
+// First element of this wave's share in a lane-strided loop (wave-uniform).
+__device__ __forceinline__ int wave_first(int tid) { return __builtin_amdgcn_readfirstlane(tid & ~63); }
+
+// Copy src[0, n) to LDS dst[0, n) with direct-to-LDS loads: in each step a
+// wave copies 64 consecutive dwords, lane l's to (wave base + 4 l).  The loop
+// bound and both bases are wave-uniform, so only the lane predicate is vector
+// work.
 __device__ __forceinline__ void dma_block(float *dst, const float *src, int n, int tid, int nt) {
   const int lane = tid & 63;
-  for (int d = tid; d < n; d += nt) __builtin_amdgcn_global_load_lds(src + d, EPK_LDS(dst + (d - lane)), 4, 0, 0);
+  for (int b = wave_first(tid); b < n; b += nt)
+    if (b + lane < n) __builtin_amdgcn_global_load_lds(src + b + lane, EPK_LDS(dst + b), 4, 0, 0);
 }
 
 // Stage NC * nf dwords of the rows src[ids[i]] (ids already in LDS) into
-// dst[i][NC].  Two ids are read per pass so that their LDS reads overlap.
+// dst[i][NC].  A lane's dword d = tid + j nt sits in row d / NC, column
+// d % NC; both advance by fixed steps from one iteration to the next, so no
+// division runs inside the loop.
 template <int NC>
 __device__ __forceinline__ void dma_rows(float *dst, const float *__restrict__ src, const int32_t *ids, int nf, int tid,
                                          int nt) {
   const int lane = tid & 63;
   const int nd = nf * NC;
-  int d = tid;
-  for (; d + nt < nd; d += 2 * nt) {
-    const int v0 = d / NC, v1 = (d + nt) / NC;
-    const int i0 = ids[v0], i1 = ids[v1];
-    __builtin_amdgcn_global_load_lds(src + int64_t(i0) * NC + (d - NC * v0), EPK_LDS(dst + (d - lane)), 4, 0, 0);
-    __builtin_amdgcn_global_load_lds(src + int64_t(i1) * NC + (d + nt - NC * v1), EPK_LDS(dst + (d + nt - lane)), 4,
-                                     0, 0);
-  }
-  if (d < nd) {
-    const int v0 = d / NC;
-    __builtin_amdgcn_global_load_lds(src + int64_t(ids[v0]) * NC + (d - NC * v0), EPK_LDS(dst + (d - lane)), 4, 0, 0);
+  const int sv = nt / NC, sc = nt - NC * (nt / NC);
+  int v = tid / NC, c = tid - NC * (tid / NC);
+  for (int b = wave_first(tid); b < nd; b += nt) {
+    if (b + lane < nd)
+      __builtin_amdgcn_global_load_lds(src + (int64_t(ids[v]) * NC + c), EPK_LDS(dst + b), 4, 0, 0);
+    v += sv;
+    c += sc;
+    if (c >= NC) {
+      c -= NC;
+      ++v;
+    }
   }
 }
 
@@ -365,10 +372,10 @@ __device__ __forceinline__ void stage_sidx(const DevPlan &P, const PartHdr &h, i
 
 // Forward compute stage.  st holds the part's states; the per-vertex sums go
 // to acc (acc may be st when q_new is not written); flx: cap * 5 floats.
+// Per-edge fluxes of a part from the staged states into flx (then a barrier).
 template <int G, int EPT>
-__device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, float *acc, float *flx,
-                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
-                                            const float4 eg[EPT], int tid, int nt) {
+__device__ __forceinline__ void edge_stage_fwd(const PartHdr &h, const float *st, float *flx, const uint32_t ew[EPT],
+                                               const float4 eg[EPT], int tid, int nt) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int j = tid + k * nt;
@@ -381,7 +388,13 @@ __device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, f
     }
   }
   lds_sync();
+}
 
+template <int G, int EPT>
+__device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, float *acc, float *flx,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
+  edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
   for (int i = tid; i < h.U; i += nt) {
     float s[5];
     vertex_sum_fwd(flx, inc, lo, i, s);
@@ -407,10 +420,11 @@ __device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, con
 
 // Adjoint compute stage.  st: states, gs: upstream gradients (overwritten by
 // the per-vertex sums); vu, vv: cap * 5 floats each.
+// Per-edge adjoint values of a part into vu, vv (then a barrier).
 template <int G, int EPT>
-__device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, float *gs, float *vu, float *vv,
-                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
-                                            const float4 eg[EPT], int tid, int nt) {
+__device__ __forceinline__ void edge_stage_bwd(const PartHdr &h, const float *st, const float *gs, float *vu,
+                                               float *vv, const uint32_t ew[EPT], const float4 eg[EPT], int tid,
+                                               int nt) {
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int j = tid + k * nt;
@@ -431,7 +445,13 @@ __device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, f
     }
   }
   lds_sync();
+}
 
+template <int G, int EPT>
+__device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, float *gs, float *vu, float *vv,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
+  edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
   for (int i = tid; i < h.U; i += nt) {
     float s[5];
     vertex_sum_bwd(vu, vv, inc, lo, i, s);
@@ -448,11 +468,63 @@ __device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, con
   write_slots(h, gs + h.nown * 5, sidx, ws, tid, nt);
 }
 
+// Five floats of one lane to dst[0, 5) (4-byte aligned) as a 16-byte and a
+// 4-byte store.
+struct __attribute__((aligned(4))) Float4u {
+  float x, y, z, w;
+};
+__device__ __forceinline__ void store_row(float *dst, const float v[5]) {
+  *reinterpret_cast<Float4u *>(dst) = {v[0], v[1], v[2], v[3]};
+  dst[4] = v[4];
+}
+
+// The destination row of local vertex i's sum: owned vertices go to out (row
+// own0 + i), foreign ones to their workspace slot.
+__device__ __forceinline__ float *sum_row(const PartHdr &h, const int32_t *sidx, float *out, float *ws, int i) {
+  if (i < h.nown) return out + (int64_t(h.own0) + i) * 5;
+  const int f = i - h.nown;
+  return ws + (sidx ? int64_t(sidx[f]) : int64_t(h.f0) + f) * 5;
+}
+
+// Per-vertex forward sums, each lane storing its vertex's row from registers
+// (owned: r and q_new; foreign: the slot).  The sums and their order are those
+// of compute_fwd; only the LDS round trip of the result is gone.
+template <bool QNEW>
+__device__ __forceinline__ void sum_store_fwd(const PartHdr &h, const float *st, const float *flx, const uint16_t *inc,
+                                              const uint16_t *lo, const int32_t *sidx, float *__restrict__ r,
+                                              float *__restrict__ qn, float dt, float *__restrict__ ws, int tid,
+                                              int nt) {
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_fwd(flx, inc, lo, i, s);
+    store_row(sum_row(h, sidx, r, ws, i), s);
+    if constexpr (QNEW) {
+      if (i < h.nown) {
+        float t[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) t[c] = st[i * 5 + c] + dt * s[c];
+        store_row(qn + (int64_t(h.own0) + i) * 5, t);
+      }
+    }
+  }
+}
+
+// Adjoint counterpart: owned sums to gq, foreign ones to their slots.
+__device__ __forceinline__ void sum_store_bwd(const PartHdr &h, const float *vu, const float *vv, const uint16_t *inc,
+                                              const uint16_t *lo, const int32_t *sidx, float *__restrict__ gq,
+                                              float *__restrict__ ws, int tid, int nt) {
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_bwd(vu, vv, inc, lo, i, s);
+    store_row(sum_row(h, sidx, gq, ws, i), s);
+  }
+}
+
 // ---- direct kernels: one part per workgroup
 
-// LDS: st[max_u][5] | (QNEW: acc[max_u][5]) | flx[cap][5] (the ids until the
-// flux stage) | inc[2 cap] u16 | lo[nlo] u16 | sidx[max_nf], nlo = max_u + 2
-// rounded up to even.
+// LDS: st[max_u][5] | flx[cap][5] (the ids until the flux stage) |
+// inc[2 cap] u16 | lo[nlo] u16 | (vertex-major workspace: sidx[max_nf]),
+// nlo = max_u + 2 rounded up to even.  The sums leave from registers.
 template <int G, bool QNEW, int EPT>
 __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
                                                         float *__restrict__ qn, float dt, float *__restrict__ ws,
@@ -462,8 +534,7 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   if (part >= P.k) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   float *st = smem;
-  float *acc = QNEW ? st + P.max_u * 5 : st;
-  float *flx = (QNEW ? acc : st) + P.max_u * 5;
+  float *flx = st + P.max_u * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
   uint16_t *lo = inc + 2 * P.cap;
   int32_t *sidx = reinterpret_cast<int32_t *>(lo + ((P.max_u + 3) & ~1));
@@ -483,8 +554,8 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   wait_staged();
-  compute_fwd<G, EPT>(h, st, acc, flx, inc, lo, ew, eg, tid, nt);
-  write_fwd<QNEW>(h, st, acc, P.sidx ? sidx : nullptr, r, qn, dt, ws, tid, nt);
+  edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
+  sum_store_fwd<QNEW>(h, st, flx, inc, lo, P.sidx ? sidx : nullptr, r, qn, dt, ws, tid, nt);
 }
 
 // LDS: st[max_u][5] | gs[max_u][5] | vu[cap][5] (the ids until the flux
@@ -520,8 +591,8 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   dma_rows<5>(gs + h.nown * 5, gr, ids, h.nf, tid, nt);
   wait_staged();
-  compute_bwd<G, EPT>(h, st, gs, vu, vv, inc, lo, ew, eg, tid, nt);
-  write_bwd(h, gs, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
+  edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
+  sum_store_bwd(h, vu, vv, inc, lo, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
 }
 
 // ---- cache-only kernels: no LDS staging of states
@@ -533,7 +604,8 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
 // instead of an LDS copy.  Only the foreign ids (to map local to packed
 // vertex ids), the incidence lists and the per-edge values live in LDS; the
 // per-vertex sums, writes and reduction are the staged kernels' own, so the
-// results are bitwise equal.
+// results agree up to rounding (the edge arithmetic is compiled separately and
+// may fuse multiplies and adds differently).
 
 __device__ __forceinline__ int64_t packed_of(const PartHdr &h, const int32_t *ids, int l) {
   return l < h.nown ? int64_t(h.own0) + l : int64_t(ids[l - h.nown]);
@@ -701,25 +773,25 @@ __device__ __forceinline__ int pipe_part(int k, int t, int swizzle) {
 
 // LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):
 // st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | (q_new: acc[max_u][5]) |
-// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | sidx[2][max_nf] |
-// inc[2][2 cap] u16 | lo[2][nlo] u16.  Buffers are addressed by arithmetic on the one LDS base,
+// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
+// lo[2][nlo] u16 | (vertex-major workspace only: sidx[2][max_nf]).  Buffers are addressed by arithmetic on the one LDS base,
 // so every pointer stays an LDS pointer (no indexed pointer arrays).
 struct PipeLds {
   float *base;
-  int su, sf, nf, cap, nlo, o_gs, o_acc, o_f0, o_f1, o_ids;
+  int su, sf, nf, cap, nlo, o_gs, o_acc, o_f0, o_f1, o_ids, o_sx;
   __device__ float *st(int b) const { return base + b * su; }
   __device__ float *gs(int b) const { return base + o_gs + b * su; }
   __device__ float *acc() const { return base + o_acc; }
   __device__ float *f0() const { return base + o_f0; }
   __device__ float *f1() const { return base + o_f1; }
   __device__ int32_t *ids(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + b * nf; }
-  __device__ int32_t *sidx(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + (2 + b) * nf; }
   __device__ uint16_t *inc(int b) const {
-    return reinterpret_cast<uint16_t *>(base + o_ids + 4 * nf) + b * (2 * cap);
+    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + b * (2 * cap);
   }
   __device__ uint16_t *lo(int b) const {
-    return reinterpret_cast<uint16_t *>(base + o_ids + 4 * nf) + 4 * cap + b * nlo;
+    return reinterpret_cast<uint16_t *>(base + o_ids + 2 * nf) + 4 * cap + b * nlo;
   }
+  __device__ int32_t *sidx(int b) const { return reinterpret_cast<int32_t *>(base + o_sx) + b * nf; }
 };
 
 __device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd, bool qnew) {
@@ -740,6 +812,7 @@ __device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool 
   L.o_f1 = o;
   o += bwd ? L.sf : 0;
   L.o_ids = o;
+  L.o_sx = o + 2 * L.nf + 2 * L.cap + L.nlo;  // after ids, inc and lo (nlo is even)
   return L;
 }
 

@@ -31,32 +31,47 @@ namespace epk {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Must match the LDS carve-up of flux_fwd_part / flux_bwd_part.
-int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool qnew) {
+int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx) {
   const int64_t nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * ((qnew ? 10 : 5) * max_u + 5 * cap) + 2 * (2 * cap + nlo) + 4 * max_nf;
+  const int64_t b = 4 * (5 * max_u + 5 * cap) + 2 * (2 * cap + nlo) + (sidx ? 4 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
 }
-int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap) {
+int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx) {
   const int64_t nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + nlo) + 4 * max_nf;
+  const int64_t b = 4 * (10 * max_u + 10 * cap) + 2 * (2 * cap + nlo) + (sidx ? 4 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
 }
 // Mirror of the device carve-up of the pipelined kernels: two state buffers
 // (two more for the adjoint's gradients), q_new sums, one (two) edge value
-// buffer(s), two id and two slot-index buffers, two incidence lists and two
-// offset lists.
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew) {
+// buffer(s), two id buffers, two incidence lists and two offset lists, and
+// two slot-index buffers for the vertex-major workspace.
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx) {
   const int64_t su = 5 * max_u, sf = 5 * cap, nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 4 * max_nf +
-                    2 * (4 * cap + 2 * nlo);
+  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
+                    2 * (4 * cap + 2 * nlo) + (sidx ? 4 * 2 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
 }
 // Mirror of the cache-only kernels' LDS: per-edge values (two arrays for the
 // adjoint), foreign ids, incidence lists and offsets, slot indices.
-int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd) {
+int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx) {
   const int64_t nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * (bwd ? 10 : 5) * cap + 4 * max_nf + 2 * (2 * cap + nlo) + 4 * max_nf;
+  const int64_t b = 4 * (bwd ? 10 : 5) * cap + 4 * max_nf + 2 * (2 * cap + nlo) + (sidx ? 4 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
+}
+
+// LDS of every FLUX5 kernel of a plan for its workspace layout (the slot
+// indices take LDS only in the vertex-major layout).
+void set_flux_lds(epk_plan *P) {
+  const int64_t u = P->max_u, f = P->max_nf, c = P->cap;
+  const bool sx = P->vmajor;
+  P->lds_fwd = flux_fwd_lds(u, f, c, sx);
+  P->lds_fwd_qn = P->lds_fwd;  // the sums (and q_new) leave from registers
+  P->lds_bwd = flux_bwd_lds(u, f, c, sx);
+  P->lds_pipe_fwd = flux_pipe_lds(u, f, c, false, false, sx);
+  P->lds_pipe_fwd_qn = flux_pipe_lds(u, f, c, false, true, sx);
+  P->lds_pipe_bwd = flux_pipe_lds(u, f, c, true, false, sx);
+  P->lds_cached_fwd = flux_cached_lds(u, f, c, false, sx);
+  P->lds_cached_bwd = flux_cached_lds(u, f, c, true, sx);
 }
 // SpMV adjoint: y gradients, x values, per-edge values, x incidence lists and
 // offsets, x slot indices.
@@ -494,14 +509,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     const int64_t C = P->stats.cost, Lds = P->stats.loads, R = P->R;
     const int64_t Cred = int64_t(red_foreign.size());
     if (kind == EPK_FLUX5) {
-      P->lds_fwd = flux_fwd_lds(P->max_u, P->max_nf, cap, false);
-      P->lds_fwd_qn = flux_fwd_lds(P->max_u, P->max_nf, cap, true);
-      P->lds_bwd = flux_bwd_lds(P->max_u, P->max_nf, cap);
-      P->lds_pipe_fwd = flux_pipe_lds(P->max_u, P->max_nf, cap, false, false);
-      P->lds_pipe_fwd_qn = flux_pipe_lds(P->max_u, P->max_nf, cap, false, true);
-      P->lds_pipe_bwd = flux_pipe_lds(P->max_u, P->max_nf, cap, true, false);
-      P->lds_cached_fwd = flux_cached_lds(P->max_u, P->max_nf, cap, false);
-      P->lds_cached_bwd = flux_cached_lds(P->max_u, P->max_nf, cap, true);
+      set_flux_lds(P);
       const int64_t G = gstore, na = P->n_active_out;
       const int64_t meta = 32 * k + 4 * m + 4 * G * m + 4 * m + 2 * int64_t(loff.size()) + 4 * C;
       P->bytes_fwd_kernel = meta + 20 * Lds + 20 * na + 20 * C;
@@ -656,7 +664,23 @@ int epk_plan_set_slot_layout(epk_plan *p, int32_t layout) {
   epk::clear_error();
   if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
   if (layout < -1 || layout > 1) return epk::fail(EPK_EINVAL, "layout must be -1, 0 or 1");
+  const bool before = p->vmajor;
   p->vmajor = layout < 0 ? p->n_slots > 4 * p->R : layout == 1;
+  if (p->kind == EPK_FLUX5 && p->vmajor != before) {
+    // the slot indices take LDS in the vertex-major layout: resize, and keep
+    // the old layout if the kernels in use would no longer fit
+    epk::set_flux_lds(p);
+    const int64_t M = epk::kMaxLdsBytes;
+    const bool over = p->lds_fwd > M || p->lds_fwd_qn > M || p->lds_bwd > M ||
+                      (!p->staging && (p->lds_cached_fwd > M || p->lds_cached_bwd > M)) ||
+                      (p->pipe && (p->lds_pipe_fwd_qn > M || p->lds_pipe_bwd > M));
+    if (over) {
+      p->vmajor = before;
+      epk::set_flux_lds(p);
+      return epk::fail(EPK_ERANGE, "the vertex-major layout's slot indices do not fit in LDS");
+    }
+    if (p->pipe) return epk_plan_set_pipeline(p, p->pipe);  // grids follow the LDS size
+  }
   return EPK_OK;
 }
 

@@ -193,6 +193,12 @@ def test_slot_layout_choice_and_bytes():
     P.set_slot_layout(1)
     b = P.info()
     assert b["vertex_major"] == 1 and b["bytes_fwd"] == a["bytes_fwd"] and b["bytes_fwd_kernel"] > a["bytes_fwd_kernel"]
+    # the slot indices (one int32 per foreign vertex of the largest part) take LDS only when vertex-major
+    for key in ("lds_fwd", "lds_bwd"):
+        assert b[key] - a[key] in range(4 * a["max_nf"], 4 * a["max_nf"] + 16)
+    assert b["lds_pipe_bwd"] - a["lds_pipe_bwd"] in range(8 * a["max_nf"], 8 * a["max_nf"] + 16)
+    P.set_slot_layout(0)
+    assert P.info() == a
     with pytest.raises(_lib.EpkError):
         P.set_slot_layout(2)
     R = gen.rmat(scale=12, n_edges=60_000, seed=1)
