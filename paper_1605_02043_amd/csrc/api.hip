@@ -38,6 +38,7 @@ DevPlan dev_plan(const epk_plan *p) {
   P.roff = dptr<int32_t>(b, L.roff);
   P.sidx = p->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;
   P.rslot = p->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
+  P.rrec = p->vmajor ? nullptr : dptr<int32_t>(b, L.rrec);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = nullptr;
   if (p->kind == EPK_SPMV) {
@@ -71,6 +72,7 @@ DevPlan dev_plan_xreduce(const epk_plan *p) {
   P.roff = dptr<int32_t>(b, L.xroff);
   P.sidx = p->xvmajor ? dptr<int32_t>(b, L.xsidx) : nullptr;
   P.rslot = p->xvmajor ? nullptr : dptr<int32_t>(b, L.xrslot);
+  P.rrec = nullptr;  // the x class reduces through its slot lists
   P.heavy = dptr<int32_t>(b, L.xheavy);
   P.R = int32_t(p->xR);
   P.n_heavy = int32_t(p->xn_heavy);
@@ -94,6 +96,7 @@ DevPlan dev_batch(const epk_batch *bt) {
   P.roff = dptr<int32_t>(b, L.roff);
   P.sidx = bt->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;
   P.rslot = bt->vmajor ? nullptr : dptr<int32_t>(b, L.rslot);
+  P.rrec = bt->vmajor ? nullptr : dptr<int32_t>(b, L.rrec);
   P.heavy = dptr<int32_t>(b, L.heavy);
   P.iso = dptr<int32_t>(b, L.iso);
   P.m = bt->me;
@@ -147,7 +150,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   std::vector<uint32_t> eloc;
   std::vector<float> geom;
   std::vector<uint16_t> inc, loff;
-  int64_t eoff = 0, foff = 0, lofs_off = 0, rbase = 0;
+  int64_t eoff = 0, foff = 0, lofs_off = 0, rbase = 0, extra_pm = 0, extra_vm = 0;
   for (int32_t g = 0; g < n_graphs; ++g) {
     const epk_plan *p = plans[g];
     const ImageLayout &L = p->lay;
@@ -185,9 +188,12 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     B->max_u = std::max<int64_t>(B->max_u, p->max_u);
     B->max_nf = std::max<int64_t>(B->max_nf, p->max_nf);
     B->max_cap = std::max<int64_t>(B->max_cap, p->cap);
-    // the slot tables are read once per launch pair, by the part kernel or the reduction
-    B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce + 4 * p->n_slots;
-    B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce + 4 * p->n_slots;
+    // per launch pair: the slot indices (vertex-major) or the records and
+    // long slot lists (part-major); added once the layout is known
+    B->bytes_fwd += p->bytes_fwd_kernel + p->bytes_reduce;
+    B->bytes_bwd += p->bytes_bwd_kernel + p->bytes_reduce;
+    extra_pm += p->rec_delta;
+    extra_vm += 4 * p->n_slots;
     eoff += p->me;
     B->m += p->m;
     foff += C;
@@ -199,6 +205,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   B->n = B->voff[n_graphs];
   B->R = rbase;
   B->vmajor = int64_t(sidx.size()) > 4 * B->R;
+  B->bytes_fwd += B->vmajor ? extra_vm : extra_pm;
+  B->bytes_bwd += B->vmajor ? extra_vm : extra_pm;
   B->n_heavy = int64_t(heavy.size());
   B->n_iso = int64_t(iso.size());
   if (B->k >= (int64_t(1) << 31) || B->n >= (int64_t(1) << 31) || B->me >= (int64_t(1) << 31)) {
@@ -219,8 +227,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     hdr.swap(sorted);
   }
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
-  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false, B->vmajor);
-  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false, B->vmajor);
+  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, B->vmajor);
+  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, B->vmajor);
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");
@@ -242,6 +250,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   L.roff = take(roff.size() * 4);
   L.sidx = take(sidx.size() * 4);
   L.rslot = take(rslot.size() * 4);
+  const std::vector<int32_t> rrec = reduction_records(rvid, roff, rslot);
+  L.rrec = take(rrec.size() * 4);
   L.heavy = take(heavy.size() * 4);
   L.iso = take(iso.size() * 4);
   L.total = off;
@@ -259,6 +269,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   put(L.roff, roff.data(), roff.size() * 4);
   put(L.sidx, sidx.data(), sidx.size() * 4);
   put(L.rslot, rslot.data(), rslot.size() * 4);
+  put(L.rrec, rrec.data(), rrec.size() * 4);
   put(L.heavy, heavy.data(), heavy.size() * 4);
   put(L.iso, iso.data(), iso.size() * 4);
   B->ws_bytes = align256(std::max<size_t>(size_t(foff) * 5 * 4, 4));

@@ -59,7 +59,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0, pfid = 0;
-  size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, heavy = 0, iso = 0, eoff = 0;
+  size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, rrec = 0, heavy = 0, iso = 0, eoff = 0;
   // SpMV adjoint: x incidence per part, y foreign ids, x-class reduction tables
   size_t xinc = 0, xlo = 0, xlofs = 0, rfid = 0, eid = 0, xrvid = 0, xroff = 0, xsidx = 0, xrslot = 0, xheavy = 0;
   size_t total = 0;
@@ -78,6 +78,7 @@ struct DevPlan {
   const int32_t *roff;
   const int32_t *sidx;   // vertex-major workspace: slot of each foreign entry (else NULL)
   const int32_t *rslot;  // part-major workspace: the slots of each replicated vertex (else NULL)
+  const int32_t *rrec;   // part-major workspace: [R][4] {vertex, slot, slot, slot} per replicated vertex (else NULL)
   const int32_t *heavy;
   const int32_t *iso;    // batch: untouched vertices (NULL: the range [n_active, n))
   const uint16_t *xinc;  // SpMV adjoint: kernel-order edges of each local x, per part
@@ -128,6 +129,7 @@ struct epk_plan {
   // bytes without the slot tables; see plan_bytes
   int64_t bytes_fwd_kernel = 0, bytes_bwd_kernel = 0, bytes_reduce = 0, bytes_reduce_qnew = 0;
   int64_t n_slots = 0;  // foreign entries of the reduced class = workspace rows
+  int64_t rec_delta = 0;  // part-major reduction bytes with records, minus those without (see plan_bytes)
   bool vmajor = false;  // workspace layout: vertex-major (true) or part-major
   // SpMV adjoint's x-class reduction
   int64_t xR = 0, xn_heavy = 0, xn_active = 0, xn_slots = 0;
@@ -155,13 +157,19 @@ namespace epk {
 // sidx: the vertex-major workspace's slot indices take LDS too.
 int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
 int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx);
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
 int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
 void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its current layout
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
+// Reduction records, one per replicated vertex: its packed id and its (at
+// most kRecSlots) slots, -1 past the last; a first slot of -1 sends the
+// vertex to the slot lists (more slots than a record holds).
+constexpr int kRecSlots = 3;
+std::vector<int32_t> reduction_records(const std::vector<int32_t> &rvid, const std::vector<int32_t> &roff,
+                                       const std::vector<int32_t> &rslot);
 DevPlan dev_plan(const epk_plan *p);
 DevPlan dev_plan_xreduce(const epk_plan *p);  // the SpMV adjoint's x-class reduction
 DevPlan dev_batch(const epk_batch *b);

@@ -7,9 +7,9 @@
 //   2. run the per-edge task out of LDS;
 //   3. sum per-vertex partials in LDS in a fixed order (FLUX5: local
 //      incidence lists; SpMV: segmented scan over edges sorted by local y);
-//   4. write owned vertices straight to the output and the partials of
-//      foreign (replicated) vertices to workspace slots, both as contiguous
-//      blocks.
+//   4. each lane stores its vertex's sum from registers: owned vertices
+//      straight to the output, foreign (replicated) ones to their workspace
+//      slots.
 // A reduction kernel then adds, for every replicated vertex, the slots to the
 // owner's partial in ascending part order.  Nothing uses atomics on data, so
 // every result is bitwise reproducible.  No MFMA: the work is gather/scatter.
@@ -347,32 +347,14 @@ __device__ __forceinline__ void vertex_sum_bwd(const float *vu, const float *vv,
   }
 }
 
-// A part's foreign partials (nf rows of 5) to their workspace slots.
-// Part-major workspace (sidx NULL): one contiguous block at the part's slot
-// offset.  Vertex-major: sidx (in LDS) gives each foreign entry's slot, so
-// that the reduction reads each vertex's slots as one contiguous run.
-__device__ __forceinline__ void write_slots(const PartHdr &h, const float *src, const int32_t *sidx,
-                                            float *__restrict__ ws, int tid, int nt) {
-  if (!sidx) {
-    float *wo = ws + int64_t(h.f0) * 5;
-    for (int d = tid; d < h.nf * 5; d += nt) wo[d] = src[d];
-    return;
-  }
-  for (int d = tid; d < h.nf * 5; d += nt) {
-    const int i = d / 5;
-    ws[int64_t(sidx[i]) * 5 + (d - 5 * i)] = src[d];
-  }
-}
-
 // The slot indices of a part's foreign entries (vertex-major workspace only).
 __device__ __forceinline__ void stage_sidx(const DevPlan &P, const PartHdr &h, int32_t *sidx, int tid, int nt) {
   if (P.sidx)
     dma_block(reinterpret_cast<float *>(sidx), reinterpret_cast<const float *>(P.sidx + h.f0), h.nf, tid, nt);
 }
 
-// Forward compute stage.  st holds the part's states; the per-vertex sums go
-// to acc (acc may be st when q_new is not written); flx: cap * 5 floats.
-// Per-edge fluxes of a part from the staged states into flx (then a barrier).
+// Per-edge fluxes of a part from the staged states st into flx (cap rows of
+// 5), then a barrier.
 template <int G, int EPT>
 __device__ __forceinline__ void edge_stage_fwd(const PartHdr &h, const float *st, float *flx, const uint32_t ew[EPT],
                                                const float4 eg[EPT], int tid, int nt) {
@@ -390,36 +372,6 @@ __device__ __forceinline__ void edge_stage_fwd(const PartHdr &h, const float *st
   lds_sync();
 }
 
-template <int G, int EPT>
-__device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, float *acc, float *flx,
-                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
-                                            const float4 eg[EPT], int tid, int nt) {
-  edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
-  for (int i = tid; i < h.U; i += nt) {
-    float s[5];
-    vertex_sum_fwd(flx, inc, lo, i, s);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) acc[i * 5 + c] = s[c];
-  }
-  lds_sync();
-}
-
-// Forward writes of a computed part: owned sums (and q_new) to the output,
-// foreign sums to the part's workspace slots.
-template <bool QNEW>
-__device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, const float *acc, const int32_t *sidx,
-                                          float *__restrict__ r, float *__restrict__ qn, float dt,
-                                          float *__restrict__ ws, int tid, int nt) {
-  float *ro = r + int64_t(h.own0) * 5;
-  for (int d = tid; d < h.nown * 5; d += nt) {
-    ro[d] = acc[d];
-    if constexpr (QNEW) qn[int64_t(h.own0) * 5 + d] = st[d] + dt * acc[d];
-  }
-  write_slots(h, acc + h.nown * 5, sidx, ws, tid, nt);
-}
-
-// Adjoint compute stage.  st: states, gs: upstream gradients (overwritten by
-// the per-vertex sums); vu, vv: cap * 5 floats each.
 // Per-edge adjoint values of a part into vu, vv (then a barrier).
 template <int G, int EPT>
 __device__ __forceinline__ void edge_stage_bwd(const PartHdr &h, const float *st, const float *gs, float *vu,
@@ -447,35 +399,35 @@ __device__ __forceinline__ void edge_stage_bwd(const PartHdr &h, const float *st
   lds_sync();
 }
 
-template <int G, int EPT>
-__device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, float *gs, float *vu, float *vv,
-                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
-                                            const float4 eg[EPT], int tid, int nt) {
-  edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
-  for (int i = tid; i < h.U; i += nt) {
-    float s[5];
-    vertex_sum_bwd(vu, vv, inc, lo, i, s);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) gs[i * 5 + c] = s[c];
-  }
-  lds_sync();
-}
-
-__device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, const int32_t *sidx,
-                                          float *__restrict__ gq, float *__restrict__ ws, int tid, int nt) {
-  float *go = gq + int64_t(h.own0) * 5;
-  for (int d = tid; d < h.nown * 5; d += nt) go[d] = gs[d];
-  write_slots(h, gs + h.nown * 5, sidx, ws, tid, nt);
-}
-
-// Five floats of one lane to dst[0, 5) (4-byte aligned) as a 16-byte and a
-// 4-byte store.
+// A row of NC floats of one lane, 4-byte aligned: for NC = 5 one 16-byte and
+// one 4-byte access instead of five 4-byte ones (a wave's rows are scattered,
+// so every access instruction costs the cache lines it touches).
 struct __attribute__((aligned(4))) Float4u {
   float x, y, z, w;
 };
-__device__ __forceinline__ void store_row(float *dst, const float v[5]) {
-  *reinterpret_cast<Float4u *>(dst) = {v[0], v[1], v[2], v[3]};
-  dst[4] = v[4];
+template <int NC = 5>
+__device__ __forceinline__ void store_row(float *dst, const float *v) {
+  if constexpr (NC == 5) {
+    *reinterpret_cast<Float4u *>(dst) = {v[0], v[1], v[2], v[3]};
+    dst[4] = v[4];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) dst[c] = v[c];
+  }
+}
+template <int NC = 5>
+__device__ __forceinline__ void load_row(const float *src, float *v) {
+  if constexpr (NC == 5) {
+    const Float4u a = *reinterpret_cast<const Float4u *>(src);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = src[4];
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = src[c];
+  }
 }
 
 // The destination row of local vertex i's sum: owned vertices go to out (row
@@ -487,8 +439,8 @@ __device__ __forceinline__ float *sum_row(const PartHdr &h, const int32_t *sidx,
 }
 
 // Per-vertex forward sums, each lane storing its vertex's row from registers
-// (owned: r and q_new; foreign: the slot).  The sums and their order are those
-// of compute_fwd; only the LDS round trip of the result is gone.
+// (owned: r and q_new; foreign: the slot), so no LDS round trip or barrier
+// follows the sums.
 template <bool QNEW>
 __device__ __forceinline__ void sum_store_fwd(const PartHdr &h, const float *st, const float *flx, const uint16_t *inc,
                                               const uint16_t *lo, const int32_t *sidx, float *__restrict__ r,
@@ -772,16 +724,14 @@ __device__ __forceinline__ int pipe_part(int k, int t, int swizzle) {
 }
 
 // LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):
-// st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | (q_new: acc[max_u][5]) |
-// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
+// st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
 // lo[2][nlo] u16 | (vertex-major workspace only: sidx[2][max_nf]).  Buffers are addressed by arithmetic on the one LDS base,
 // so every pointer stays an LDS pointer (no indexed pointer arrays).
 struct PipeLds {
   float *base;
-  int su, sf, nf, cap, nlo, o_gs, o_acc, o_f0, o_f1, o_ids, o_sx;
+  int su, sf, nf, cap, nlo, o_gs, o_f0, o_f1, o_ids, o_sx;
   __device__ float *st(int b) const { return base + b * su; }
   __device__ float *gs(int b) const { return base + o_gs + b * su; }
-  __device__ float *acc() const { return base + o_acc; }
   __device__ float *f0() const { return base + o_f0; }
   __device__ float *f1() const { return base + o_f1; }
   __device__ int32_t *ids(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + b * nf; }
@@ -794,7 +744,7 @@ struct PipeLds {
   __device__ int32_t *sidx(int b) const { return reinterpret_cast<int32_t *>(base + o_sx) + b * nf; }
 };
 
-__device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd, bool qnew) {
+__device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd) {
   PipeLds L;
   L.base = smem;
   L.su = P.max_u * 5;
@@ -805,8 +755,6 @@ __device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool 
   int o = 2 * L.su;
   L.o_gs = o;
   o += bwd ? 2 * L.su : 0;
-  L.o_acc = o;
-  o += qnew ? L.su : 0;
   L.o_f0 = o;
   o += L.sf;
   L.o_f1 = o;
@@ -822,7 +770,7 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
                                                      int swizzle) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const PipeLds L = pipe_lds(P, smem, false, QNEW);
+  const PipeLds L = pipe_lds(P, smem, false);
   uint32_t ew[EPT], ewn[EPT];
   float4 eg[EPT], egn[EPT];
 
@@ -841,25 +789,22 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
-  // The writes of part t-1 open iteration t: issued right after the wait,
-  // they complete while part t is computed instead of delaying the next wait.
-  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};  // part t-1 (none yet: writes nothing)
-  int t = 0;
-  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+  // The barrier of the wait that opens iteration t also frees buffer nb and
+  // the edge-value buffer: every wave has finished part t-1 by then (its sums
+  // left from registers at the end of the previous iteration).
+  for (int t = 0; pipe_part(P.k, t, swizzle) >= 0; ++t) {
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
-    write_fwd<QNEW>(hp, L.st(nb), QNEW ? L.acc() : L.st(nb), P.sidx ? L.sidx(nb) : nullptr, r, qn, dt, ws, tid,
-                    nt);  // W(t-1)
-    lds_sync();                                           // buffers nb and acc are free again
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));   // H(t+3)
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);     // B(t+1)
     stage_sidx(P, h1, L.sidx(nb), tid, nt);
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);                  // A(t+2)
-    compute_fwd<G, EPT>(h0, L.st(b), QNEW ? L.acc() : L.st(b), L.f0(), L.inc(b), L.lo(b), ew, eg, tid, nt);  // C(t)
-    hp = h0;
+    edge_stage_fwd<G, EPT>(h0, L.st(b), L.f0(), ew, eg, tid, nt);  // C(t), then its writes
+    sum_store_fwd<QNEW>(h0, L.st(b), L.f0(), L.inc(b), L.lo(b), P.sidx ? L.sidx(b) : nullptr, r, qn, dt, ws, tid,
+                        nt);
     h0 = h1;
     h1 = h2;
 #pragma unroll
@@ -868,8 +813,6 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
       eg[k] = egn[k];
     }
   }
-  const int pb = (t + 1) & 1;  // buffer of part t-1
-  write_fwd<QNEW>(hp, L.st(pb), QNEW ? L.acc() : L.st(pb), P.sidx ? L.sidx(pb) : nullptr, r, qn, dt, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
 }
 
@@ -879,7 +822,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
                                                      float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const PipeLds L = pipe_lds(P, smem, true, false);
+  const PipeLds L = pipe_lds(P, smem, true);
   uint32_t ew[EPT], ewn[EPT];
   float4 eg[EPT], egn[EPT];
 
@@ -898,14 +841,10 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
-  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};
-  int t = 0;
-  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+  for (int t = 0; pipe_part(P.k, t, swizzle) >= 0; ++t) {
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
-    write_bwd(hp, L.gs(nb), P.sidx ? L.sidx(nb) : nullptr, gq, ws, tid, nt);
-    lds_sync();
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);
     stage_state(h1, gr, L.gs(nb), L.ids(nb), tid, nt);
@@ -913,8 +852,8 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);
-    compute_bwd<G, EPT>(h0, L.st(b), L.gs(b), L.f0(), L.f1(), L.inc(b), L.lo(b), ew, eg, tid, nt);
-    hp = h0;
+    edge_stage_bwd<G, EPT>(h0, L.st(b), L.gs(b), L.f0(), L.f1(), ew, eg, tid, nt);
+    sum_store_bwd(h0, L.f0(), L.f1(), L.inc(b), L.lo(b), P.sidx ? L.sidx(b) : nullptr, gq, ws, tid, nt);
     h0 = h1;
     h1 = h2;
 #pragma unroll
@@ -923,7 +862,6 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
       eg[k] = egn[k];
     }
   }
-  write_bwd(hp, L.gs((t + 1) & 1), P.sidx ? L.sidx((t + 1) & 1) : nullptr, gq, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);
 }
 
@@ -1075,8 +1013,8 @@ __global__ void __launch_bounds__(1024) spmv_adj_kernel(DevPlan P, const float *
 
 // Light vertices (<= kHeavySlots partials): one thread per vertex,
 // r_v = (((own + s_1) + s_2) + ...) in ascending part order; a vertex's slots
-// are one contiguous run of a vertex-major workspace, or found through rslot
-// in a part-major one.  Heavy vertices: one workgroup
+// are one contiguous run of a vertex-major workspace, or, in a part-major
+// one, listed in its record (up to kRecSlots) or found through rslot.  Heavy vertices: one workgroup
 // each, strided partial sums then a fixed tree.  Untouched vertices are
 // zeroed here as well.
 template <int NC, bool QNEW>
@@ -1086,36 +1024,74 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restric
   __shared__ float red[kHeavyBlock];
   if (int(blockIdx.x) < nb_light) {
     const int64_t rho = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (rho < P.R) {
+    if (rho < P.R && P.rrec && P.rrec[4 * rho + 1] >= 0) {
+      // up to kRecSlots slots, all in the vertex's record: one dependent load
+      // fewer than the slot lists; absent slots re-read the first with
+      // weight 0 (the sum's bits are those of the list path)
+      const int4 rec = reinterpret_cast<const int4 *>(P.rrec)[rho];
+      const int64_t o = int64_t(rec.x) * NC;
+      const int sl[3] = {rec.y, rec.z, rec.w};
+      float s[NC], v[3][NC];
+      load_row<NC>(r + o, s);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) load_row<NC>(ws + int64_t(sl[u] < 0 ? rec.y : sl[u]) * NC, v[u]);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const float w = sl[u] < 0 ? 0.f : 1.f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
+      }
+      store_row<NC>(r + o, s);
+      if constexpr (QNEW) {
+        float qv[NC], t[NC];
+        load_row<NC>(q + o, qv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) t[c] = qv[c] + dt * s[c];
+        store_row<NC>(qn + o, t);
+      }
+    } else if (rho < P.R) {
       const int s0 = P.roff[rho], s1 = P.roff[rho + 1];
       if (s1 - s0 > kHeavySlots) return;
       const int64_t o = int64_t(P.rvid[rho]) * NC;
       float s[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) s[c] = r[o + c];
+      load_row<NC>(r + o, s);
       if (P.rslot) {
-        for (int t = s0; t < s1; t += 4) {  // four slot ids per batch of loads
-          int sl[4];
+        for (int t = s0; t < s1; t += 4) {
+          // four slots per batch of loads, with no branch: past the vertex's
+          // last slot, its first slot is read again with weight 0 (adding
+          // zero leaves the sum's bits unchanged)
+          int in[4], sl[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) sl[u] = t + u < s1 ? P.rslot[t + u] : -1;
+          for (int u = 0; u < 4; ++u) in[u] = -int(t + u < s1);
+          asm volatile("" : "+v"(in[0]), "+v"(in[1]), "+v"(in[2]), "+v"(in[3]));
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (sl[u] >= 0) {
+          for (int u = 0; u < 4; ++u) sl[u] = P.rslot[s0 + ((t + u - s0) & in[u])];
+          float v[4][NC];
 #pragma unroll
-              for (int c = 0; c < NC; ++c) s[c] += ws[int64_t(sl[u]) * NC + c];
-            }
+          for (int u = 0; u < 4; ++u) load_row<NC>(ws + int64_t(sl[u]) * NC, v[u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float w = __int_as_float(0x3f800000 & in[u]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
+          }
         }
       } else {
         const float *wp = ws + int64_t(s0) * NC;
         for (int t = 0; t < s1 - s0; ++t) {
+          float v[NC];
+          load_row<NC>(wp + t * NC, v);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) s[c] += wp[t * NC + c];
+          for (int c = 0; c < NC; ++c) s[c] += v[c];
         }
       }
+      store_row<NC>(r + o, s);
+      if constexpr (QNEW) {
+        float qv[NC], t[NC];
+        load_row<NC>(q + o, qv);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        r[o + c] = s[c];
-        if constexpr (QNEW) qn[o + c] = q[o + c] + dt * s[c];
+        for (int c = 0; c < NC; ++c) t[c] = qv[c] + dt * s[c];
+        store_row<NC>(qn + o, t);
       }
     } else if (rho < int64_t(P.R) + (P.iso ? P.n_iso : P.n - P.n_active)) {
       const int64_t v = P.iso ? int64_t(P.iso[rho - P.R]) : int64_t(P.n_active) + (rho - P.R);

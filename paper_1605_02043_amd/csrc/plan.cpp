@@ -42,12 +42,13 @@ int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx) {
   return (b + 15) & ~int64_t(15);
 }
 // Mirror of the device carve-up of the pipelined kernels: two state buffers
-// (two more for the adjoint's gradients), q_new sums, one (two) edge value
-// buffer(s), two id buffers, two incidence lists and two offset lists, and
-// two slot-index buffers for the vertex-major workspace.
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx) {
+// (two more for the adjoint's gradients), one (two) edge value buffer(s),
+// two id buffers, two incidence lists and two offset lists, and two
+// slot-index buffers for the vertex-major workspace.  The sums (and q_new)
+// leave from registers, so q_new takes no LDS.
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx) {
   const int64_t su = 5 * max_u, sf = 5 * cap, nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
+  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
                     2 * (4 * cap + 2 * nlo) + (sidx ? 4 * 2 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
 }
@@ -59,6 +60,18 @@ int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bo
   return (b + 15) & ~int64_t(15);
 }
 
+std::vector<int32_t> reduction_records(const std::vector<int32_t> &rvid, const std::vector<int32_t> &roff,
+                                       const std::vector<int32_t> &rslot) {
+  std::vector<int32_t> rec(rvid.size() * 4, -1);
+  for (size_t v = 0; v < rvid.size(); ++v) {
+    rec[4 * v] = rvid[v];
+    const int32_t n = roff[v + 1] - roff[v];
+    if (n > kRecSlots) continue;
+    for (int32_t t = 0; t < n; ++t) rec[4 * v + 1 + t] = rslot[size_t(roff[v] + t)];
+  }
+  return rec;
+}
+
 // LDS of every FLUX5 kernel of a plan for its workspace layout (the slot
 // indices take LDS only in the vertex-major layout).
 void set_flux_lds(epk_plan *P) {
@@ -67,9 +80,9 @@ void set_flux_lds(epk_plan *P) {
   P->lds_fwd = flux_fwd_lds(u, f, c, sx);
   P->lds_fwd_qn = P->lds_fwd;  // the sums (and q_new) leave from registers
   P->lds_bwd = flux_bwd_lds(u, f, c, sx);
-  P->lds_pipe_fwd = flux_pipe_lds(u, f, c, false, false, sx);
-  P->lds_pipe_fwd_qn = flux_pipe_lds(u, f, c, false, true, sx);
-  P->lds_pipe_bwd = flux_pipe_lds(u, f, c, true, false, sx);
+  P->lds_pipe_fwd = flux_pipe_lds(u, f, c, false, sx);
+  P->lds_pipe_fwd_qn = P->lds_pipe_fwd;
+  P->lds_pipe_bwd = flux_pipe_lds(u, f, c, true, sx);
   P->lds_cached_fwd = flux_cached_lds(u, f, c, false, sx);
   P->lds_cached_bwd = flux_cached_lds(u, f, c, true, sx);
 }
@@ -87,13 +100,15 @@ int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
 
 // Algorithmic bytes of one launch under the plan's workspace layout:
 // which = 0 forward part kernel, 1 adjoint part kernel, 2 reduction.  The
-// vertex-major layout adds the slot-index reads to the part kernels, the
-// part-major one the slot-list reads to the reduction.
+// vertex-major layout adds the slot-index reads to the part kernels; the
+// part-major reduction reads a record per replicated vertex instead of its
+// id and offsets, and the slot lists only for vertices with more slots than
+// a record holds.
 int64_t plan_bytes(const epk_plan *p, int which) {
   const int64_t ids = 4 * p->n_slots;
   if (which == 0) return p->bytes_fwd_kernel + (p->vmajor ? ids : 0);
   if (which == 1) return p->kind == EPK_FLUX5 ? p->bytes_bwd_kernel + (p->vmajor ? ids : 0) : 0;
-  return p->bytes_reduce + (p->vmajor ? 0 : ids);
+  return p->vmajor ? p->bytes_reduce : p->bytes_reduce + p->rec_delta;
 }
 
 namespace {
@@ -462,6 +477,18 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.roff = take(roff.size() * 4);
     L.sidx = take(sidx.size() * 4);
     L.rslot = take(rslot.size() * 4);
+    const std::vector<int32_t> rrec = reduction_records(rvid, roff, rslot);
+    L.rrec = take(rrec.size() * 4);
+    {
+      // part-major reduction: a 16-byte record replaces the id (4) and the
+      // offsets (4 (R + 1)); vertices with more slots also read offsets and list
+      int64_t extra = 0;
+      for (size_t v = 0; v < rvid.size(); ++v) {
+        const int64_t ns = roff[v + 1] - roff[v];
+        if (ns > kRecSlots) extra += 8 + 4 * ns;
+      }
+      P->rec_delta = 16 * int64_t(rvid.size()) + extra - 4 * int64_t(rvid.size()) - 4 * (int64_t(rvid.size()) + 1);
+    }
     L.xinc = take(xinc.size() * 2);
     L.xlo = take(xlo.size() * 2);
     L.xlofs = take(xlofs.size() * 4);
@@ -488,6 +515,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     put(P->image, L.roff, roff);
     put(P->image, L.sidx, sidx);
     put(P->image, L.rslot, rslot);
+    put(P->image, L.rrec, rrec);
     if (kind == EPK_SPMV) {
       put(P->image, L.xinc, xinc);
       put(P->image, L.xlo, xlo);

@@ -184,15 +184,21 @@ def test_plan_handles_empty_graph():
 
 
 def test_slot_layout_choice_and_bytes():
-    """Meshes keep the part-major workspace, power-law SpMV takes the vertex-major one;
-    the slot tables are counted once per forward either way."""
+    """Meshes keep the part-major workspace, power-law SpMV takes the vertex-major one.
+    Vertex-major: the part kernel reads one slot index per foreign entry (4 C bytes).
+    Part-major: the reduction reads a 16-byte record per replicated vertex in place of
+    its id and offsets (4 R + 4 (R + 1)); mesh vertices never have more than the
+    record's three slots, so no slot list is read."""
     T = gen.tet_mesh(8, 8, 8, seed=0)
     P = Plan(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
+    st = P.stats
+    R, C = st["replicated"], st["cost"]
     a = P.info()
     assert a["vertex_major"] == 0
     P.set_slot_layout(1)
     b = P.info()
-    assert b["vertex_major"] == 1 and b["bytes_fwd"] == a["bytes_fwd"] and b["bytes_fwd_kernel"] > a["bytes_fwd_kernel"]
+    assert b["vertex_major"] == 1 and b["bytes_fwd_kernel"] - a["bytes_fwd_kernel"] == 4 * C
+    assert a["bytes_fwd"] - b["bytes_fwd"] == (16 * R - 4 * R - 4 * (R + 1)) - 4 * C
     # the slot indices (one int32 per foreign vertex of the largest part) take LDS only when vertex-major
     for key in ("lds_fwd", "lds_bwd"):
         assert b[key] - a[key] in range(4 * a["max_nf"], 4 * a["max_nf"] + 16)
