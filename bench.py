@@ -65,6 +65,8 @@ def _args():
     ap.add_argument("--cap", type=int, default=256)
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
+    ap.add_argument("--slot-layout", type=int, default=-1, choices=[-1, 0, 1],
+                    help="FLUX5 workspace layout: -1 the plan's choice, 0 part-major, 1 vertex-major")
     ap.add_argument("--staging", type=int, default=1,
                     help="1: stage each part's states in LDS; 0: the cache-only variant (states read through L1/L2)")
     ap.add_argument("--pipe", type=int, default=0,
@@ -128,7 +130,7 @@ def C_void(x):
     return ctypes.c_void_p(x)
 
 
-def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, staging=1):
+def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, staging=1, layout=-1):
     from paper_1605_02043_amd import Plan
 
     import gen
@@ -136,6 +138,8 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, sta
     t0 = time.perf_counter()
     P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order)
     P.set_launch(wg, swizzle)
+    if layout != -1:
+        P.set_slot_layout(layout)
     P.upload("cuda")
     if not staging:
         P.set_staging(0)
@@ -321,7 +325,8 @@ def main():
     G = gen.workload(args.workload, seed=0)
     m = len(G["edges"])
     print(f"# workload {args.workload}: n={G['n']} m={m}", file=sys.stderr, flush=True)
-    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe, args.staging)
+    ep = run_order(G, "ep", args.cap, args.steps, args.warmup, torch, args.wg, args.swizzle, args.pipe, args.staging,
+                   args.slot_layout)
     print(f"# ep: {ep['wall_ms_per_step']:.4f} ms/step kernels {ep['kernel_ms']}", file=sys.stderr, flush=True)
     default = None
     if not args.no_default_order:
@@ -367,6 +372,7 @@ def main():
             "launch": (f"pipelined persistent, grid {ep['info']['grid_pipe_fwd']} fwd / {ep['info']['grid_pipe_bwd']} bwd"
                        if ep["info"]["pipe"] else "one workgroup per part"),
             "staging": "LDS" if ep["info"]["staging"] else "caches only (no LDS staging of states)",
+            "slot_layout": "vertex-major" if ep["info"]["vertex_major"] else "part-major",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -614,7 +620,8 @@ def bench_batch(args, torch):
     out = _common(args, "edges/s, batched persistent FLUX5 fwd+bwd over 256 uneven meshes, HIP-graph replay, 1 MI355X",
                   m / wall, wall * 1e3,
                   {"workload": f"batch256: 256 2D/3D mesh graphs, vertex counts log-uniform in [1024, 65536], "
-                               f"total n={n}, m={m}, capacities autotuned per size decile", "graphs": 256})
+                               f"total n={n}, m={m}, one capacity autotuned over {{64, 128, 256, 512}} by timing the batched launch",
+                               "graphs": 256})
     out["roofline"] = {"bound": "hbm", "kernel": "graph replay (persistent fwd + reduce + persistent bwd + reduce)",
                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                        "traffic": None}

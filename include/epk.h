@@ -278,12 +278,18 @@ int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, flo
                        void *stream);
 void epk_batch_destroy(epk_batch *b);
 
-/* Capacity selection: for every graph, time the forward at each capacity in
- * caps[n_caps] and keep the fastest per size class (graphs grouped by
- * vertex-count decile); results are cached in cache_path (a text file,
- * NULL = no cache).  d_scratch (scratch_bytes) is caller-allocated device
- * memory for the trials; EPK_ERANGE if it is too small.  Synchronises the
- * stream.  chosen_cap[n_graphs] out; chosen_wg may be NULL.               */
+/* Capacity selection for a batch: for each capacity in caps[n_caps], build
+ * every graph's EP plan at that capacity, merge them into one batch and time
+ * its pipelined forward + adjoint launch (median of 5 timings of 5 passes);
+ * the fastest capacity is chosen for all graphs, since a batched launch sizes
+ * every workgroup's LDS for its largest parts.  Timings within 2% of the
+ * fastest count as ties, won by the fewest algorithmic bytes.  Results are
+ * cached in cache_path (a text file of key|cap wg lines, NULL = no cache).
+ * d_scratch (scratch_bytes) is caller-allocated device memory for the trials
+ * (a whole batch's image, workspace and three state arrays); a capacity that
+ * does not fit is skipped, EPK_ERANGE if none fits.  Plans are built on up to
+ * 16 host threads.  Synchronises the stream.  chosen_cap[n_graphs] out;
+ * chosen_wg may be NULL.                                                  */
 int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps,
                  const char *cache_path, void *d_scratch, size_t scratch_bytes, void *stream,
                  int32_t *chosen_cap, int32_t *chosen_wg);

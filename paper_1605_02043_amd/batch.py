@@ -74,9 +74,10 @@ class Batch:
 
 
 def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", scratch_bytes=None):
-    """Pick a capacity per vertex-count decile by timing the forward kernel.
+    """Pick the batch's capacity by timing the batched forward + adjoint launch at each candidate.
 
-    graphs: list of dicts with 'edges', 'n', 'geom'.  Returns (caps[n_graphs], wgs[n_graphs]).
+    graphs: list of dicts with 'edges', 'n', 'geom'.  Returns (caps[n_graphs], wgs[n_graphs]), one
+    capacity for all graphs (the batched launch sizes every workgroup for its largest parts).
     """
     import torch
 
@@ -87,8 +88,8 @@ def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", s
         gs, k = make_graph(g["edges"], g["n"], g["geom"])
         arr[i] = gs
         keep.append(k)
-        need = max(need, len(g["edges"]) * 64 + g["n"] * 80 + (1 << 20))
-    scratch = torch.empty(scratch_bytes or need, dtype=torch.uint8, device=device)
+        need += len(g["edges"]) * 160 + g["n"] * 80  # a whole batch's image, workspace and states
+    scratch = torch.empty(scratch_bytes or need + (64 << 20), dtype=torch.uint8, device=device)
     c = np.asarray(caps, dtype=np.int32)
     out_cap = np.zeros(len(graphs), dtype=np.int32)
     out_wg = np.zeros(len(graphs), dtype=np.int32)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -10,6 +11,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "epk_internal.h"
@@ -227,8 +229,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     hdr.swap(sorted);
   }
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
-  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, B->vmajor);
-  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, B->vmajor);
+  B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false, B->vmajor);
+  B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false, B->vmajor);
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");
@@ -284,55 +286,108 @@ __global__ void fill_kernel(float *p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
-static std::string tune_key(const epk_graph &g, const int32_t *caps, int32_t n_caps) {
+// Key of a tuning problem: the graphs' sizes and the candidate capacities.
+static std::string tune_key(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps) {
   std::ostringstream os;
-  os << g.n_vertices << ' ' << g.n_edges << ' ' << g.geom_ncomp;
+  int64_t n = 0, m = 0;
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    n += gs[g].n_vertices;
+    m += gs[g].n_edges;
+  }
+  os << "batch " << n_graphs << ' ' << n << ' ' << m;
   for (int32_t i = 0; i < n_caps; ++i) os << ' ' << caps[i];
   return os.str();
 }
 
-// Median forward time (ms) of one graph at one capacity, run out of d_scratch.
-static int time_forward(const epk_graph &g, int32_t cap, void *d_scratch, size_t scratch_bytes, hipStream_t s,
-                        float *ms_out, int32_t *wg_out) {
-  epk_plan *p = nullptr;
-  int st = epk_plan_create(&g, cap, EPK_ORDER_EP, EPK_FLUX5, &p);
+// Plans of all graphs at one capacity, built on up to 16 host threads.
+static int build_plans(const epk_graph *gs, int32_t n_graphs, int32_t cap, std::vector<epk_plan *> &plans) {
+  plans.assign(size_t(n_graphs), nullptr);
+  const int nth = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  std::vector<int> status(static_cast<size_t>(nth), EPK_OK);
+  std::vector<std::string> msg(static_cast<size_t>(nth));
+  std::atomic<int32_t> next{0};
+  auto work = [&](int w) {
+    for (int32_t g; (g = next.fetch_add(1)) < n_graphs;) {
+      const int st = epk_plan_create(&gs[g], cap, EPK_ORDER_EP, EPK_FLUX5, &plans[size_t(g)]);
+      if (st && status[size_t(w)] == EPK_OK) {
+        status[size_t(w)] = st;
+        msg[size_t(w)] = epk_last_error();  // the error text is per thread
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nth; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto &t : pool) t.join();
+  for (int w = 0; w < nth; ++w)
+    if (status[size_t(w)]) {
+      for (epk_plan *p : plans) epk_plan_destroy(p);
+      plans.clear();
+      return fail(status[size_t(w)], msg[size_t(w)]);
+    }
+  return EPK_OK;
+}
+
+// Time (ms) of one batched forward + adjoint pass over all graphs at one
+// capacity, run out of d_scratch: the median of 5 timings of 5 back-to-back
+// passes.  EPK_ERANGE if the batch does not fit in the scratch memory or in
+// LDS.  Also returns the batch's algorithmic bytes per pass.
+static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, void *d_scratch, size_t scratch_bytes,
+                      hipStream_t s, float *ms_out, int32_t *wg_out, int64_t *bytes_out) {
+  std::vector<epk_plan *> plans;
+  int st = build_plans(gs, n_graphs, cap, plans);
+  if (st) return st;
+  epk_batch *b = nullptr;
+  st = epk_batch_create(n_graphs, plans.data(), &b);
+  const int32_t wg = plans[0]->wg;
+  for (epk_plan *p : plans) epk_plan_destroy(p);
   if (st) return st;
   size_t img = 0, ws = 0;
-  epk_plan_device_bytes(p, &img, &ws);
-  const size_t state = align256(size_t(g.n_vertices) * 5 * 4);
-  if (img + ws + 2 * state > scratch_bytes) {
-    epk_plan_destroy(p);
+  epk_batch_device_bytes(b, &img, &ws);
+  const size_t state = align256(size_t(b->n) * 5 * 4);
+  if (img + ws + 3 * state > scratch_bytes) {
+    epk_batch_destroy(b);
     return fail(EPK_ERANGE, "autotune scratch too small");
   }
   uint8_t *base = static_cast<uint8_t *>(d_scratch);
   float *q = reinterpret_cast<float *>(base + img + ws);
-  float *r = reinterpret_cast<float *>(base + img + ws + state);
-  const int64_t nq = int64_t(g.n_vertices) * 5;
-  if (nq) hipLaunchKernelGGL(fill_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, q, nq, 1.0f);
-  st = epk_plan_upload(p, base, s);
+  float *g = reinterpret_cast<float *>(base + img + ws + state);
+  float *o = reinterpret_cast<float *>(base + img + ws + 2 * state);
+  const int64_t nq = b->n * 5;
+  if (nq) {
+    hipLaunchKernelGGL(fill_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, q, nq, 1.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, g, nq, 1.0f);
+  }
+  st = epk_batch_upload(b, base, s);
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   std::vector<float> t;
-  for (int it = 0; it < 8 && !st; ++it) {
+  constexpr int kPasses = 5;
+  for (int it = 0; it < 6 && !st; ++it) {  // the first timing warms up
     (void)hipEventRecord(e0, s);
-    st = epk_forward(p, q, r, 0.f, nullptr, base + img, s);
+    for (int l = 0; l < kPasses && !st; ++l) {
+      st = epk_batch_forward(b, q, o, base + img, s);
+      if (!st) st = epk_batch_backward(b, q, g, o, base + img, s);
+    }
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (it >= 2) t.push_back(ms);
+    if (it >= 1) t.push_back(ms / kPasses);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!st) {
     std::sort(t.begin(), t.end());
     *ms_out = t[t.size() / 2];
-    *wg_out = p->wg;
+    *wg_out = wg;
+    *bytes_out = b->bytes_fwd + b->bytes_bwd;
   }
-  epk_plan_destroy(p);
+  epk_batch_destroy(b);
   return st;
 }
+
 
 }  // namespace epk
 
@@ -571,62 +626,61 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
   if (!d_scratch) return fail(EPK_EINVAL, "d_scratch is NULL");
   for (int32_t i = 0; i < n_caps; ++i)
     if (caps[i] < 1) return fail(EPK_EINVAL, "capacities must be >= 1");
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    const int v = validate_graph(&gs[g], EPK_FLUX5);
+    if (v) return v;
+    if (gs[g].geom_ncomp != 4) return fail(EPK_EINVAL, "batched graphs need 4 geometry components");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // size classes: vertex-count deciles
-  std::vector<int32_t> order(static_cast<size_t>(n_graphs));
-  for (int32_t i = 0; i < n_graphs; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return gs[a].n_vertices < gs[b].n_vertices; });
-  const int n_cls = std::min<int32_t>(10, n_graphs);
-  std::map<std::string, std::pair<int32_t, int32_t>> cache;
+  const std::string key = tune_key(gs, n_graphs, caps, n_caps);
+  int32_t best_cap = 0, best_wg = 0;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       const size_t bar = line.find('|');
-      if (bar == std::string::npos) continue;
+      if (bar == std::string::npos || line.substr(0, bar) != key) continue;
       std::istringstream rest(line.substr(bar + 1));
       int32_t c = 0, w = 0;
-      if (rest >> c >> w) cache[line.substr(0, bar)] = {c, w};
-    }
-  }
-  bool dirty = false;
-  for (int cl = 0; cl < n_cls; ++cl) {
-    const int32_t lo = int32_t(int64_t(cl) * n_graphs / n_cls), hi = int32_t(int64_t(cl + 1) * n_graphs / n_cls);
-    if (lo >= hi) continue;
-    const epk_graph &rep = gs[order[(lo + hi) / 2]];  // median member stands for the class
-    const std::string key = tune_key(rep, caps, n_caps);
-    int32_t best_cap = caps[0], best_wg = 0;
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      best_cap = it->second.first;
-      best_wg = it->second.second;
-    } else {
-      float best = 1e30f;
-      for (int32_t i = 0; i < n_caps; ++i) {
-        float ms = 0;
-        int32_t wg = 0;
-        const int st = time_forward(rep, caps[i], d_scratch, scratch_bytes, s, &ms, &wg);
-        if (st == EPK_ERANGE) continue;  // capacity not runnable here
-        if (st) return st;
-        if (ms < best) {
-          best = ms;
-          best_cap = caps[i];
-          best_wg = wg;
-        }
+      if (rest >> c >> w) {
+        best_cap = c;
+        best_wg = w;
       }
-      if (best >= 1e30f) return fail(EPK_ERANGE, "no capacity could be timed");
-      cache[key] = {best_cap, best_wg};
-      dirty = true;
-    }
-    for (int32_t j = lo; j < hi; ++j) {
-      chosen_cap[order[j]] = best_cap;
-      if (chosen_wg) chosen_wg[order[j]] = best_wg;
     }
   }
-  if (cache_path && dirty) {
-    std::ofstream outf(cache_path, std::ios::trunc);
-    for (const auto &kv : cache) outf << kv.first << '|' << kv.second.first << ' ' << kv.second.second << '\n';
+  if (!best_cap) {
+    // one capacity for the whole batch: its launch sizes every workgroup's
+    // LDS for the largest parts, so mixing capacities only lowers occupancy.
+    // Timings within kTie of the fastest count as equal; among those the
+    // fewest algorithmic bytes win, so that timing noise does not decide.
+    constexpr float kTie = 1.02f;
+    std::vector<float> ms(size_t(n_caps), 1e30f);
+    std::vector<int32_t> wgs(size_t(n_caps), 0);
+    std::vector<int64_t> bytes(size_t(n_caps), 0);
+    float best = 1e30f;
+    for (int32_t i = 0; i < n_caps; ++i) {
+      const int st = time_batch(gs, n_graphs, caps[i], d_scratch, scratch_bytes, s, &ms[i], &wgs[i], &bytes[i]);
+      if (st == EPK_ERANGE) continue;  // capacity not runnable here
+      if (st) return st;
+      best = std::min(best, ms[i]);
+    }
+    if (best >= 1e30f) return fail(EPK_ERANGE, "no capacity could be timed (scratch or LDS too small)");
+    int64_t fewest = -1;
+    for (int32_t i = 0; i < n_caps; ++i)
+      if (ms[i] <= best * kTie && (fewest < 0 || bytes[i] < fewest)) {
+        fewest = bytes[i];
+        best_cap = caps[i];
+        best_wg = wgs[i];
+      }
+    if (cache_path) {
+      std::ofstream outf(cache_path, std::ios::app);
+      outf << key << '|' << best_cap << ' ' << best_wg << '\n';
+    }
+  }
+  clear_error();
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    chosen_cap[g] = best_cap;
+    if (chosen_wg) chosen_wg[g] = best_wg;
   }
   return EPK_OK;
 }

@@ -157,7 +157,7 @@ namespace epk {
 // sidx: the vertex-major workspace's slot indices take LDS too.
 int64_t flux_fwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
 int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx);
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx);
 int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
 void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its current layout
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);

@@ -7,9 +7,9 @@
 //   2. run the per-edge task out of LDS;
 //   3. sum per-vertex partials in LDS in a fixed order (FLUX5: local
 //      incidence lists; SpMV: segmented scan over edges sorted by local y);
-//   4. each lane stores its vertex's sum from registers: owned vertices
-//      straight to the output, foreign (replicated) ones to their workspace
-//      slots.
+//   4. owned vertices' sums go straight to the output, foreign (replicated)
+//      ones to workspace slots: from registers in the one-part-per-workgroup
+//      kernels, from LDS one iteration later in the pipelined ones.
 // A reduction kernel then adds, for every replicated vertex, the slots to the
 // owner's partial in ascending part order.  Nothing uses atomics on data, so
 // every result is bitwise reproducible.  No MFMA: the work is gather/scatter.
@@ -347,6 +347,23 @@ __device__ __forceinline__ void vertex_sum_bwd(const float *vu, const float *vv,
   }
 }
 
+// A part's foreign partials (nf rows of 5) to their workspace slots.
+// Part-major workspace (sidx NULL): one contiguous block at the part's slot
+// offset.  Vertex-major: sidx (in LDS) gives each foreign entry's slot, so
+// that the reduction reads each vertex's slots as one contiguous run.
+__device__ __forceinline__ void write_slots(const PartHdr &h, const float *src, const int32_t *sidx,
+                                            float *__restrict__ ws, int tid, int nt) {
+  if (!sidx) {
+    float *wo = ws + int64_t(h.f0) * 5;
+    for (int d = tid; d < h.nf * 5; d += nt) wo[d] = src[d];
+    return;
+  }
+  for (int d = tid; d < h.nf * 5; d += nt) {
+    const int i = d / 5;
+    ws[int64_t(sidx[i]) * 5 + (d - 5 * i)] = src[d];
+  }
+}
+
 // The slot indices of a part's foreign entries (vertex-major workspace only).
 __device__ __forceinline__ void stage_sidx(const DevPlan &P, const PartHdr &h, int32_t *sidx, int tid, int nt) {
   if (P.sidx)
@@ -372,6 +389,40 @@ __device__ __forceinline__ void edge_stage_fwd(const PartHdr &h, const float *st
   lds_sync();
 }
 
+// The pipelined kernels' compute stage: the sums go to acc in LDS (acc may be
+// st when q_new is not written) and leave with write_fwd one iteration later.
+// On gfx950 a wait for loads also waits for stores, so stores issued at the
+// end of an iteration would stall the next iteration's wait.
+template <int G, int EPT>
+__device__ __forceinline__ void compute_fwd(const PartHdr &h, const float *st, float *acc, float *flx,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
+  edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_fwd(flx, inc, lo, i, s);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[i * 5 + c] = s[c];
+  }
+  lds_sync();
+}
+
+// Forward writes of a computed part: owned sums (and q_new) to the output,
+// foreign sums to the part's workspace slots.
+template <bool QNEW>
+__device__ __forceinline__ void write_fwd(const PartHdr &h, const float *st, const float *acc, const int32_t *sidx,
+                                          float *__restrict__ r, float *__restrict__ qn, float dt,
+                                          float *__restrict__ ws, int tid, int nt) {
+  float *ro = r + int64_t(h.own0) * 5;
+  for (int d = tid; d < h.nown * 5; d += nt) {
+    ro[d] = acc[d];
+    if constexpr (QNEW) qn[int64_t(h.own0) * 5 + d] = st[d] + dt * acc[d];
+  }
+  write_slots(h, acc + h.nown * 5, sidx, ws, tid, nt);
+}
+
+// Adjoint compute stage.  st: states, gs: upstream gradients (overwritten by
+// the per-vertex sums); vu, vv: cap * 5 floats each.
 // Per-edge adjoint values of a part into vu, vv (then a barrier).
 template <int G, int EPT>
 __device__ __forceinline__ void edge_stage_bwd(const PartHdr &h, const float *st, const float *gs, float *vu,
@@ -397,6 +448,27 @@ __device__ __forceinline__ void edge_stage_bwd(const PartHdr &h, const float *st
     }
   }
   lds_sync();
+}
+
+template <int G, int EPT>
+__device__ __forceinline__ void compute_bwd(const PartHdr &h, const float *st, float *gs, float *vu, float *vv,
+                                            const uint16_t *inc, const uint16_t *lo, const uint32_t ew[EPT],
+                                            const float4 eg[EPT], int tid, int nt) {
+  edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
+  for (int i = tid; i < h.U; i += nt) {
+    float s[5];
+    vertex_sum_bwd(vu, vv, inc, lo, i, s);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) gs[i * 5 + c] = s[c];
+  }
+  lds_sync();
+}
+
+__device__ __forceinline__ void write_bwd(const PartHdr &h, const float *gs, const int32_t *sidx,
+                                          float *__restrict__ gq, float *__restrict__ ws, int tid, int nt) {
+  float *go = gq + int64_t(h.own0) * 5;
+  for (int d = tid; d < h.nown * 5; d += nt) go[d] = gs[d];
+  write_slots(h, gs + h.nown * 5, sidx, ws, tid, nt);
 }
 
 // A row of NC floats of one lane, 4-byte aligned: for NC = 5 one 16-byte and
@@ -724,14 +796,16 @@ __device__ __forceinline__ int pipe_part(int k, int t, int swizzle) {
 }
 
 // LDS carve-up of the pipelined kernels (host mirror: flux_pipe_lds):
-// st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
+// st[2][max_u][5] | (adjoint: gs[2][max_u][5]) | (q_new: acc[max_u][5]) |
+// f0[cap][5] | (adjoint: f1[cap][5]) | ids[2][max_nf] | inc[2][2 cap] u16 |
 // lo[2][nlo] u16 | (vertex-major workspace only: sidx[2][max_nf]).  Buffers are addressed by arithmetic on the one LDS base,
 // so every pointer stays an LDS pointer (no indexed pointer arrays).
 struct PipeLds {
   float *base;
-  int su, sf, nf, cap, nlo, o_gs, o_f0, o_f1, o_ids, o_sx;
+  int su, sf, nf, cap, nlo, o_gs, o_acc, o_f0, o_f1, o_ids, o_sx;
   __device__ float *st(int b) const { return base + b * su; }
   __device__ float *gs(int b) const { return base + o_gs + b * su; }
+  __device__ float *acc() const { return base + o_acc; }
   __device__ float *f0() const { return base + o_f0; }
   __device__ float *f1() const { return base + o_f1; }
   __device__ int32_t *ids(int b) const { return reinterpret_cast<int32_t *>(base + o_ids) + b * nf; }
@@ -744,7 +818,7 @@ struct PipeLds {
   __device__ int32_t *sidx(int b) const { return reinterpret_cast<int32_t *>(base + o_sx) + b * nf; }
 };
 
-__device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd) {
+__device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool bwd, bool qnew) {
   PipeLds L;
   L.base = smem;
   L.su = P.max_u * 5;
@@ -755,6 +829,8 @@ __device__ __forceinline__ PipeLds pipe_lds(const DevPlan &P, float *smem, bool 
   int o = 2 * L.su;
   L.o_gs = o;
   o += bwd ? 2 * L.su : 0;
+  L.o_acc = o;
+  o += qnew ? L.su : 0;
   L.o_f0 = o;
   o += L.sf;
   L.o_f1 = o;
@@ -770,7 +846,7 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
                                                      int swizzle) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const PipeLds L = pipe_lds(P, smem, false);
+  const PipeLds L = pipe_lds(P, smem, false, QNEW);
   uint32_t ew[EPT], ewn[EPT];
   float4 eg[EPT], egn[EPT];
 
@@ -789,22 +865,25 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
-  // The barrier of the wait that opens iteration t also frees buffer nb and
-  // the edge-value buffer: every wave has finished part t-1 by then (its sums
-  // left from registers at the end of the previous iteration).
-  for (int t = 0; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+  // The writes of part t-1 open iteration t: issued right after the wait,
+  // they complete while part t is computed instead of delaying the next wait.
+  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};  // part t-1 (none yet: writes nothing)
+  int t = 0;
+  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
+    write_fwd<QNEW>(hp, L.st(nb), QNEW ? L.acc() : L.st(nb), P.sidx ? L.sidx(nb) : nullptr, r, qn, dt, ws, tid,
+                    nt);  // W(t-1)
+    lds_sync();                                           // buffers nb and acc are free again
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));   // H(t+3)
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);     // B(t+1)
     stage_sidx(P, h1, L.sidx(nb), tid, nt);
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);                  // A(t+2)
-    edge_stage_fwd<G, EPT>(h0, L.st(b), L.f0(), ew, eg, tid, nt);  // C(t), then its writes
-    sum_store_fwd<QNEW>(h0, L.st(b), L.f0(), L.inc(b), L.lo(b), P.sidx ? L.sidx(b) : nullptr, r, qn, dt, ws, tid,
-                        nt);
+    compute_fwd<G, EPT>(h0, L.st(b), QNEW ? L.acc() : L.st(b), L.f0(), L.inc(b), L.lo(b), ew, eg, tid, nt);  // C(t)
+    hp = h0;
     h0 = h1;
     h1 = h2;
 #pragma unroll
@@ -813,6 +892,8 @@ __global__ void __launch_bounds__(256) flux_fwd_pipe(DevPlan P, const float *__r
       eg[k] = egn[k];
     }
   }
+  const int pb = (t + 1) & 1;  // buffer of part t-1
+  write_fwd<QNEW>(hp, L.st(pb), QNEW ? L.acc() : L.st(pb), P.sidx ? L.sidx(pb) : nullptr, r, qn, dt, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
 }
 
@@ -822,7 +903,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
                                                      float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const PipeLds L = pipe_lds(P, smem, true);
+  const PipeLds L = pipe_lds(P, smem, true, false);
   uint32_t ew[EPT], ewn[EPT];
   float4 eg[EPT], egn[EPT];
 
@@ -841,10 +922,14 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
 
-  for (int t = 0; pipe_part(P.k, t, swizzle) >= 0; ++t) {
+  PartHdr hp = {0, 0, 0, 0, 0, 0, 0, 0};
+  int t = 0;
+  for (; pipe_part(P.k, t, swizzle) >= 0; ++t) {
     const int b = t & 1, nb = b ^ 1;
     wait_staged();
     const PartHdr h2 = hdr_unpack(hv);
+    write_bwd(hp, L.gs(nb), P.sidx ? L.sidx(nb) : nullptr, gq, ws, tid, nt);
+    lds_sync();
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));
     stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);
     stage_state(h1, gr, L.gs(nb), L.ids(nb), tid, nt);
@@ -852,8 +937,8 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
     stage_ids(P, h2, L.ids(b), tid, nt);
-    edge_stage_bwd<G, EPT>(h0, L.st(b), L.gs(b), L.f0(), L.f1(), ew, eg, tid, nt);
-    sum_store_bwd(h0, L.f0(), L.f1(), L.inc(b), L.lo(b), P.sidx ? L.sidx(b) : nullptr, gq, ws, tid, nt);
+    compute_bwd<G, EPT>(h0, L.st(b), L.gs(b), L.f0(), L.f1(), L.inc(b), L.lo(b), ew, eg, tid, nt);
+    hp = h0;
     h0 = h1;
     h1 = h2;
 #pragma unroll
@@ -862,6 +947,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
       eg[k] = egn[k];
     }
   }
+  write_bwd(hp, L.gs((t + 1) & 1), P.sidx ? L.sidx((t + 1) & 1) : nullptr, gq, ws, tid, nt);
   __builtin_amdgcn_s_waitcnt(0);
 }
 

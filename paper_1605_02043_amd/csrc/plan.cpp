@@ -42,13 +42,14 @@ int64_t flux_bwd_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool sidx) {
   return (b + 15) & ~int64_t(15);
 }
 // Mirror of the device carve-up of the pipelined kernels: two state buffers
-// (two more for the adjoint's gradients), one (two) edge value buffer(s),
-// two id buffers, two incidence lists and two offset lists, and two
-// slot-index buffers for the vertex-major workspace.  The sums (and q_new)
-// leave from registers, so q_new takes no LDS.
-int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx) {
+// (two more for the adjoint's gradients), q_new sums, one (two) edge value
+// buffer(s), two id buffers, two incidence lists and two offset lists, and
+// two slot-index buffers for the vertex-major workspace.  (These kernels write
+// a part's sums from LDS one iteration later, so that the stores overlap the
+// next part's compute instead of the next wait.)
+int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool qnew, bool sidx) {
   const int64_t su = 5 * max_u, sf = 5 * cap, nlo = (max_u + 3) & ~int64_t(1);
-  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
+  const int64_t b = 4 * ((bwd ? 4 : 2) * su + (qnew ? su : 0) + (bwd ? 2 : 1) * sf) + 4 * 2 * max_nf +
                     2 * (4 * cap + 2 * nlo) + (sidx ? 4 * 2 * max_nf : 0);
   return (b + 15) & ~int64_t(15);
 }
@@ -80,9 +81,9 @@ void set_flux_lds(epk_plan *P) {
   P->lds_fwd = flux_fwd_lds(u, f, c, sx);
   P->lds_fwd_qn = P->lds_fwd;  // the sums (and q_new) leave from registers
   P->lds_bwd = flux_bwd_lds(u, f, c, sx);
-  P->lds_pipe_fwd = flux_pipe_lds(u, f, c, false, sx);
-  P->lds_pipe_fwd_qn = P->lds_pipe_fwd;
-  P->lds_pipe_bwd = flux_pipe_lds(u, f, c, true, sx);
+  P->lds_pipe_fwd = flux_pipe_lds(u, f, c, false, false, sx);
+  P->lds_pipe_fwd_qn = flux_pipe_lds(u, f, c, false, true, sx);
+  P->lds_pipe_bwd = flux_pipe_lds(u, f, c, true, false, sx);
   P->lds_cached_fwd = flux_cached_lds(u, f, c, false, sx);
   P->lds_cached_bwd = flux_cached_lds(u, f, c, true, sx);
 }
