@@ -201,14 +201,26 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, sta
         cold["step"] = float(np.median([e[0].elapsed_time(e[4]) for e in cev]))
     step_gpu = float(np.mean([e[0].elapsed_time(e[4]) for e in evs]))
     # each stage alone, K back-to-back launches between two events: the launch gaps of a
-    # step (kernel switches, event records) drop out, as in a kernel trace
+    # step (kernel switches, event records) drop out, as in a kernel trace.  With graph
+    # timing the K launches are one HIP graph, so host launch gaps drop out as well.
     loop = {}
     for i, nm in enumerate(names):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            _stage(P, torch, i, q, gr, r, gq)
-        e1.record()
+        if GRAPH_TIMING:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(steps):
+                    _stage(P, torch, i, q, gr, r, gq)
+            g.replay()  # warm replay
+            torch.cuda.synchronize()
+            e0.record()
+            g.replay()
+            e1.record()
+        else:
+            e0.record()
+            for _ in range(steps):
+                _stage(P, torch, i, q, gr, r, gq)
+            e1.record()
         torch.cuda.synchronize()
         loop[nm] = e0.elapsed_time(e1) / steps
     info = P.info()
@@ -376,7 +388,8 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "timing": f"HIP events around {args.steps} back-to-back launches of the kernel",
+                     "timing": (f"HIP events around a HIP-graph replay of {args.steps} back-to-back launches of the kernel"
+                                if GRAPH_TIMING else f"HIP events around {args.steps} back-to-back launches of the kernel"),
                      "traffic": traffic["ep"][dom]["bytes"] if traffic else None},
         "kernels": per_kernel,
         "gpu_ms_per_step": ep["gpu_ms_per_step"],
