@@ -151,6 +151,40 @@ __device__ __forceinline__ void dma_rows(float *dst, const float *__restrict__ s
   }
 }
 
+// Two arrays staged with the same indices (the adjoint's states and upstream
+// gradients): one loop, so the ids and addresses are computed once for both.
+__device__ __forceinline__ void dma_block2(float *dst0, const float *src0, float *dst1, const float *src1, int n,
+                                           int tid, int nt) {
+  const int lane = tid & 63;
+  for (int b = wave_first(tid); b < n; b += nt)
+    if (b + lane < n) {
+      __builtin_amdgcn_global_load_lds(src0 + b + lane, EPK_LDS(dst0 + b), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(src1 + b + lane, EPK_LDS(dst1 + b), 4, 0, 0);
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void dma_rows2(float *dst0, const float *__restrict__ src0, float *dst1,
+                                          const float *__restrict__ src1, const int32_t *ids, int nf, int tid, int nt) {
+  const int lane = tid & 63;
+  const int nd = nf * NC;
+  const int sv = nt / NC, sc = nt - NC * (nt / NC);
+  int v = tid / NC, c = tid - NC * (tid / NC);
+  for (int b = wave_first(tid); b < nd; b += nt) {
+    if (b + lane < nd) {
+      const int64_t e = int64_t(ids[v]) * NC + c;
+      __builtin_amdgcn_global_load_lds(src0 + e, EPK_LDS(dst0 + b), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(src1 + e, EPK_LDS(dst1 + b), 4, 0, 0);
+    }
+    v += sv;
+    c += sc;
+    if (c >= NC) {
+      c -= NC;
+      ++v;
+    }
+  }
+}
+
 __device__ __forceinline__ void wait_staged() {
   __builtin_amdgcn_s_waitcnt(0);  // all direct-to-LDS loads of this wave have landed
   __syncthreads();
@@ -610,10 +644,8 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   const PartHdr h = hdr_unpack(hv);
   stage_sidx(P, h, sidx, tid, nt);
   dma_incidence(inc, lo, P, h, tid, nt);
-  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  dma_block(gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
-  dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
-  dma_rows<5>(gs + h.nown * 5, gr, ids, h.nf, tid, nt);
+  dma_block2(st, q + int64_t(h.own0) * 5, gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_rows2<5>(st + h.nown * 5, q, gs + h.nown * 5, gr, ids, h.nf, tid, nt);
   wait_staged();
   edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
   sum_store_bwd(h, vu, vv, inc, lo, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
