@@ -151,6 +151,18 @@ __device__ __forceinline__ void dma_rows(float *dst, const float *__restrict__ s
   }
 }
 
+// Two blocks of different lengths in one loop: fewer loop steps than two
+// loops, and both blocks' loads are issued side by side.
+__device__ __forceinline__ void dma_pair(float *dst0, const float *src0, int n0, float *dst1, const float *src1, int n1,
+                                         int tid, int nt) {
+  const int lane = tid & 63;
+  const int n = max(n0, n1);
+  for (int b = wave_first(tid); b < n; b += nt) {
+    if (b + lane < n0) __builtin_amdgcn_global_load_lds(src0 + b + lane, EPK_LDS(dst0 + b), 4, 0, 0);
+    if (b + lane < n1) __builtin_amdgcn_global_load_lds(src1 + b + lane, EPK_LDS(dst1 + b), 4, 0, 0);
+  }
+}
+
 // Two arrays staged with the same indices (the adjoint's states and upstream
 // gradients): one loop, so the ids and addresses are computed once for both.
 __device__ __forceinline__ void dma_block2(float *dst0, const float *src0, float *dst1, const float *src1, int n,
@@ -607,9 +619,11 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   wait_staged();
   const PartHdr h = hdr_unpack(hv);
   // owned and foreign rows, incidence lists and offsets, slot indices
-  stage_sidx(P, h, sidx, tid, nt);
-  dma_incidence(inc, lo, P, h, tid, nt);
-  dma_block(st, q + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_pair(st, q + int64_t(h.own0) * 5, h.nown * 5, reinterpret_cast<float *>(inc),
+           reinterpret_cast<const float *>(P.inc) + h.e0, h.ne, tid, nt);
+  dma_pair(reinterpret_cast<float *>(lo), reinterpret_cast<const float *>(P.loff) + (h.lofs >> 1), (h.U + 2) >> 1,
+           reinterpret_cast<float *>(sidx), reinterpret_cast<const float *>(P.sidx) + h.f0, P.sidx ? h.nf : 0, tid,
+           nt);
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   wait_staged();
   edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
@@ -643,7 +657,9 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   wait_staged();
   const PartHdr h = hdr_unpack(hv);
   stage_sidx(P, h, sidx, tid, nt);
-  dma_incidence(inc, lo, P, h, tid, nt);
+  dma_pair(reinterpret_cast<float *>(inc), reinterpret_cast<const float *>(P.inc) + h.e0, h.ne,
+           reinterpret_cast<float *>(lo), reinterpret_cast<const float *>(P.loff) + (h.lofs >> 1), (h.U + 2) >> 1, tid,
+           nt);
   dma_block2(st, q + int64_t(h.own0) * 5, gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
   dma_rows2<5>(st + h.nown * 5, q, gs + h.nown * 5, gr, ids, h.nf, tid, nt);
   wait_staged();
