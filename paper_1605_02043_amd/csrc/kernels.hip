@@ -317,6 +317,14 @@ __device__ __forceinline__ void stage_state(const PartHdr &h, const float *__res
   dma_rows<5>(dst + h.nown * 5, src, ids, h.nf, tid, nt);
 }
 
+// The same rows of two state arrays (states and upstream gradients) in one pass.
+__device__ __forceinline__ void stage_state2(const PartHdr &h, const float *__restrict__ src0, float *dst0,
+                                             const float *__restrict__ src1, float *dst1, const int32_t *ids, int tid,
+                                             int nt) {
+  dma_block2(dst0, src0 + int64_t(h.own0) * 5, dst1, src1 + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
+  dma_rows2<5>(dst0 + h.nown * 5, src0, dst1 + h.nown * 5, src1, ids, h.nf, tid, nt);
+}
+
 // Sum of the signed per-edge fluxes at local vertex i, over its incidence
 // list in ascending (edge, side) order: the first kIncBatch entries, then
 // their rows, each as one batch of LDS reads.
@@ -964,8 +972,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
   PartHdr h1 = hdr_unpack(hv);
   hv = hdr_lanes(P, pipe_part(P.k, 2, swizzle));
   stage_ids(P, h1, L.ids(1), tid, nt);
-  stage_state(h0, q, L.st(0), L.ids(0), tid, nt);
-  stage_state(h0, gr, L.gs(0), L.ids(0), tid, nt);
+  stage_state2(h0, q, L.st(0), gr, L.gs(0), L.ids(0), tid, nt);
   stage_sidx(P, h0, L.sidx(0), tid, nt);
   dma_incidence(L.inc(0), L.lo(0), P, h0, tid, nt);
   load_edges<G, EPT>(P, h0, tid, nt, ew, eg);
@@ -979,8 +986,7 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
     write_bwd(hp, L.gs(nb), P.sidx ? L.sidx(nb) : nullptr, gq, ws, tid, nt);
     lds_sync();
     hv = hdr_lanes(P, pipe_part(P.k, t + 3, swizzle));
-    stage_state(h1, q, L.st(nb), L.ids(nb), tid, nt);
-    stage_state(h1, gr, L.gs(nb), L.ids(nb), tid, nt);
+    stage_state2(h1, q, L.st(nb), gr, L.gs(nb), L.ids(nb), tid, nt);
     stage_sidx(P, h1, L.sidx(nb), tid, nt);
     dma_incidence(L.inc(nb), L.lo(nb), P, h1, tid, nt);
     load_edges<G, EPT>(P, h1, tid, nt, ewn, egn);
