@@ -227,6 +227,22 @@ def test_edge_2d_geometry_and_hub():
     _small_case(star, n, 16, order="input")
 
 
+def test_edge_dense_parts_and_heavy_hub():
+    """Parts with more foreign ids and more vertices than a workgroup has lanes (several id,
+    row and sum steps per lane; two edges per lane at capacity 512), and a hub with more
+    partials than the light reduction path takes (the one-workgroup-per-vertex path)."""
+    rng = np.random.default_rng(7)
+    n, m = 1200, 5000  # capacity 512: up to 394 foreign ids and 397 vertices in one part
+    u = rng.integers(0, n, m)
+    v = (u + 1 + rng.integers(0, n - 1, m)) % n
+    say("case dense parts cap=512")
+    _small_case(np.stack([u, v], 1), n, 512, seed=7)
+    n = 300
+    star = np.stack([np.zeros(n - 1, int), np.arange(1, n)], 1)  # capacity 2: the hub has 149 partials
+    say("case heavy hub cap=2")
+    _small_case(star, n, 2, dim=2)
+
+
 def test_permute_rows_roundtrip():
     from paper_1605_02043_amd import permute_rows
 

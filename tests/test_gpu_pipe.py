@@ -123,6 +123,13 @@ def test_pipe_edge_cases():
     _small(star, 300, 16, 2, 3)
     say("case pipe hub 3D input order")
     _small(star, 300, 16, 3, 4, order="input")
+    say("case pipe heavy hub cap=2")
+    _small(star, 300, 2, 2, 5)
+    n, m = 1200, 5000  # capacity 512: more foreign ids and vertices per part than lanes
+    u = rng.integers(0, n, m)
+    v = (u + 1 + rng.integers(0, n - 1, m)) % n
+    say("case pipe dense parts cap=512")
+    _small(np.stack([u, v], 1), n, 512, 3, 7)
 
 
 def test_pipe_grid64_2d_both_orders():
