@@ -630,8 +630,8 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   dma_pair(st, q + int64_t(h.own0) * 5, h.nown * 5, reinterpret_cast<float *>(inc),
            reinterpret_cast<const float *>(P.inc) + h.e0, h.ne, tid, nt);
   dma_pair(reinterpret_cast<float *>(lo), reinterpret_cast<const float *>(P.loff) + (h.lofs >> 1), (h.U + 2) >> 1,
-           reinterpret_cast<float *>(sidx), reinterpret_cast<const float *>(P.sidx) + h.f0, P.sidx ? h.nf : 0, tid,
-           nt);
+           reinterpret_cast<float *>(sidx), P.sidx ? reinterpret_cast<const float *>(P.sidx + h.f0) : nullptr,
+           P.sidx ? h.nf : 0, tid, nt);
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
   wait_staged();
   edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
