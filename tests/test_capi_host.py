@@ -3,6 +3,7 @@ entry points validate their inputs, and the C++ partitioner and packing agree
 bit for bit with the oracle."""
 
 import ctypes as C
+import json
 import os
 import re
 
@@ -159,6 +160,26 @@ def _check_layout(edges, n, cap, geom, kind="flux5", n_x=0, order="ep"):
     stt = P.stats
     assert stt["loads"] == sum(int(L["own_count"][p].sum()) for p in range(stt["n_parts"])) + len(fi)
     assert stt["cost"] == len(fi)
+
+
+def test_plan_layout_hand_derived_three_parts(golden_dir):
+    """The C++ plan packs the hand-derived case of tests/golden/cpack_three_parts.json identically
+    (the default order at capacity 3 is exactly that case's partition)."""
+    with open(os.path.join(golden_dir, "cpack_three_parts.json")) as f:
+        G = json.load(f)
+    E = np.array(G["edges"], dtype=np.int32)
+    geom = np.tile(np.array([[1.0, 0.0, 0.0, 1.0]], dtype=np.float32), (len(E), 1))
+    P = Plan(E, G["n"], G["capacity"], geom, order="input")
+    part, task = P.part_of_edge()
+    assert part.tolist() == G["part"] and task.tolist() == G["task"]
+    assert P.perm().tolist() == G["perm"]
+    L = P.layout()
+    fo, fi = L["foreign_offset"], L["foreign_ids"]
+    assert L["own_begin"][:, 0].tolist() == G["own_begin"] and L["own_count"][:, 0].tolist() == G["own_count"]
+    assert [fi[fo[p]:fo[p + 1]].tolist() for p in range(len(G["own_begin"]))] == G["foreign"]
+    st_ = P.stats
+    assert (st_["loads"], st_["cost"], st_["replicated"], st_["slots"]) == (G["loads"], G["cost"], G["replicated"],
+                                                                         G["slots"])
 
 
 def test_layout_parity_flux():

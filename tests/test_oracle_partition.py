@@ -52,6 +52,22 @@ def test_fig1_brute_force_optimum(golden_dir):
     assert best == G["optimal_cost"]
 
 
+def test_cpack_hand_derived_three_parts(golden_dir):
+    """cpack.layout against a case derived by hand (tests/golden/cpack_three_parts.json):
+    three parts, a vertex next touched by part 1 ahead of two next touched by part 2,
+    an unshared vertex first, an isolated vertex last."""
+    with open(os.path.join(golden_dir, "cpack_three_parts.json")) as f:
+        G = json.load(f)
+    E = np.array(G["edges"])
+    lay = cpack.layout(E, G["n"], G["part"], G["task"])
+    assert lay["perm"].tolist() == G["perm"]
+    for p, info in enumerate(lay["parts"]):
+        assert info["own0"][0] == G["own_begin"][p] and info["nown"][0] == G["own_count"][p]
+        assert list(info["foreign"][0]) == G["foreign"][p]
+    c = cost.partition_cost(E, G["n"], np.array(G["part"]), 3)
+    assert (c["loads"], c["cost"], c["replicated"], c["slots"]) == (G["loads"], G["cost"], G["replicated"], G["slots"])
+
+
 def test_fig1_ggp_finds_the_ep_schedule(golden_dir):
     G = _fig1(golden_dir)
     E, n = np.array(G["edges"]), G["n"]
