@@ -328,6 +328,21 @@ def test_multilevel_fig1(golden_dir):
     part, task, k = multilevel.partition(E, n, G["threads_per_block"])
     assert k == 2
     assert cost.partition_cost(E, n, part, k)["loads"] == G["ep_loads"] == 7
+    # every split into two parts of 3 edges, enumerated: the cost-1 optimum is unique up to
+    # the part labels, so the output is fixed exactly once labelled (the part holding edge 0
+    # is part 0; edge ids ascend inside a part)
+    import itertools
+
+    optima = []
+    for first in itertools.combinations(range(6), 3):
+        p = np.ones(6, dtype=np.int64)
+        p[list(first)] = 0
+        loads = sum(len({int(w) for e in range(6) if p[e] == q for w in E[e]}) for q in (0, 1))
+        if loads == 7:
+            optima.append(p.tolist())
+    assert sorted(optima) == sorted([G["ep_parts"], [1 - x for x in G["ep_parts"]]])
+    assert part.tolist() == G["ep_parts"]
+    assert task.tolist() == [0, 1, 3, 2, 4, 5]
 
 
 @settings(max_examples=60, deadline=None)
