@@ -89,13 +89,20 @@ __device__ __forceinline__ void euler_vjp(const float *q, float n1, float n2, fl
 }
 
 // 3D edges carry the area vector A = a n (3 floats); 2D edges the unit normal.
+constexpr int geom_floats(int G) { return G == 4 ? 3 : 2; }
+
+// Geometry of edge base + t, from the wave-uniform base pointer gb = geom +
+// geom_floats(G) * base and a 32-bit lane offset t.  The address is then an
+// SGPR base plus a 32-bit VGPR offset: with 64-bit lane arithmetic the
+// compiler can read the destination register of a load still in flight as a
+// don't-care half of the address, and must wait for that load first.
 template <int G>
-__device__ __forceinline__ float4 load_geom(const float *geom, int64_t e) {
+__device__ __forceinline__ float4 load_geom(const float *gb, uint32_t t) {
   if constexpr (G == 4) {
-    const float *g = geom + 3 * e;
+    const float *g = gb + 3u * t;
     return make_float4(g[0], g[1], g[2], 0.f);
   } else {
-    const float2 g = reinterpret_cast<const float2 *>(geom)[e];
+    const float2 g = reinterpret_cast<const float2 *>(gb)[t];
     return make_float4(g.x, g.y, 0.f, 0.f);
   }
 }
@@ -266,15 +273,21 @@ __device__ __forceinline__ int64_t clamp_edge(const DevPlan &P, int e0, int ne, 
   return min(int64_t(e0) + max(min(j, ne - 1), 0), P.m - 1);
 }
 
-// Edge endpoints and geometry into registers.
+// Edge endpoints and geometry into registers, for the edges clamp_edge
+// gives: eb = min(e0, m - 1) is wave-uniform, and the lane's offset from it
+// min(max(min(j, ne - 1), 0), m - 1 - eb) is 32-bit.
 template <int G, int EPT>
 __device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, int tid, int nt, uint32_t ew[EPT],
                                            float4 eg[EPT]) {
+  const int64_t eb = min(int64_t(h.e0), P.m - 1);
+  const int lim = int(min(int64_t(h.ne - 1), P.m - 1 - eb));
+  const uint32_t *el = P.eloc + eb;
+  const float *gb = P.geom + geom_floats(G) * eb;
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
-    const int64_t e = clamp_edge(P, h.e0, h.ne, tid + k * nt);
-    ew[k] = P.eloc[e];
-    eg[k] = load_geom<G>(P.geom, e);
+    const uint32_t t = uint32_t(min(max(min(tid + k * nt, h.ne - 1), 0), max(lim, 0)));
+    ew[k] = el[t];
+    eg[k] = load_geom<G>(gb, t);
   }
 }
 
@@ -284,11 +297,13 @@ __device__ __forceinline__ void load_edges(const DevPlan &P, const PartHdr &h, i
 template <int G, int EPT>
 __device__ __forceinline__ void load_edge_block(const DevPlan &P, int64_t e0, int tid, int nt, uint32_t ew[EPT],
                                                 float4 eg[EPT]) {
+  const uint32_t *el = P.eloc + e0;
+  const float *gb = P.geom + geom_floats(G) * e0;
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
-    const int64_t e = e0 + min(tid + k * nt, P.cap - 1);
-    ew[k] = P.eloc[e];
-    eg[k] = load_geom<G>(P.geom, e);
+    const uint32_t t = uint32_t(min(tid + k * nt, P.cap - 1));
+    ew[k] = el[t];
+    eg[k] = load_geom<G>(gb, t);
   }
 }
 
@@ -1164,11 +1179,14 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restric
   __shared__ float red[kHeavyBlock];
   if (int(blockIdx.x) < nb_light) {
     const int64_t rho = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (rho < P.R && P.rrec && P.rrec[4 * rho + 1] >= 0) {
+    // The whole record is read before the branch on it, so that the rows are
+    // the second and last dependent load of the record path.
+    int4 rec = make_int4(-1, -1, -1, -1);
+    if (rho < P.R && P.rrec) rec = reinterpret_cast<const int4 *>(P.rrec)[rho];
+    if (rec.y >= 0) {
       // up to kRecSlots slots, all in the vertex's record: one dependent load
       // fewer than the slot lists; absent slots re-read the first with
       // weight 0 (the sum's bits are those of the list path)
-      const int4 rec = reinterpret_cast<const int4 *>(P.rrec)[rho];
       const int64_t o = int64_t(rec.x) * NC;
       const int sl[3] = {rec.y, rec.z, rec.w};
       float s[NC], v[3][NC];
