@@ -617,7 +617,7 @@ def bench_batch(args, torch):
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     plans = [Plan(g["edges"], g["n"], int(c), g["geom"].astype(np.float32)) for g, c in zip(graphs, caps)]
-    B = Batch(plans).upload("cuda")
+    B = Batch(plans).set_launch(int(wgs[0])).upload("cuda")
     plan_s = time.perf_counter() - t0
     q = torch.from_numpy(np.concatenate([gen.flux_state(g["n"], seed=i)[p.perm()] for i, (g, p) in
                                          enumerate(zip(graphs, plans))])).cuda()
@@ -661,7 +661,7 @@ def bench_batch(args, torch):
     out = _common(args, "edges/s, batched persistent FLUX5 fwd+bwd over 256 uneven meshes, HIP-graph replay, 1 MI355X",
                   m / wall, wall * 1e3,
                   {"workload": f"batch256: 256 2D/3D mesh graphs, vertex counts log-uniform in [1024, 65536], "
-                               f"total n={n}, m={m}, one capacity autotuned over {{64, 128, 256, 512}} by timing the batched launch",
+                               f"total n={n}, m={m}, one capacity and workgroup size autotuned over {{64, 128, 256, 512}} x {{64, 128, 256}} lanes by timing the batched launch",
                                "graphs": 256, "timing": "the timed steps captured in one HIP graph, one replay"})
     out["roofline"] = {"bound": "hbm", "kernel": "graph replay (persistent fwd + reduce + persistent bwd + reduce)",
                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,

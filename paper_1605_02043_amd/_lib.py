@@ -69,6 +69,7 @@ _SIGS = {
     "epk_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
     "epk_batch_device_bytes": (C.c_int, [_P, _SZP, _SZP]),
     "epk_batch_upload": (C.c_int, [_P, _P, _P]),
+    "epk_batch_set_launch": (C.c_int, [_P, C.c_int32]),
     "epk_batch_vertex_offsets": (C.c_int, [_P, _I64P]),
     "epk_batch_info": (C.c_int, [_P, _I64P, C.c_int32]),
     "epk_batch_forward": (C.c_int, [_P, _FP, _FP, _P, _P]),

@@ -45,6 +45,11 @@ class Batch:
         check(lib.epk_batch_info(self._h, i64p(a), 8))
         return dict(zip(["items", "grid", "lds_fwd", "bytes_fwd", "bytes_bwd", "wg", "m", "grid_bwd"], a.tolist()))
 
+    def set_launch(self, wg: int):
+        """Workgroup size of the persistent launch (64..256, multiple of 64; 0 keeps it)."""
+        check(lib.epk_batch_set_launch(self._h, int(wg)))
+        return self
+
     def upload(self, device="cuda"):
         import torch
 
@@ -74,10 +79,12 @@ class Batch:
 
 
 def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", scratch_bytes=None):
-    """Pick the batch's capacity by timing the batched forward + adjoint launch at each candidate.
+    """Pick the batch's capacity and workgroup size by timing the batched forward + adjoint
+    launch at each candidate pair.
 
     graphs: list of dicts with 'edges', 'n', 'geom'.  Returns (caps[n_graphs], wgs[n_graphs]), one
-    capacity for all graphs (the batched launch sizes every workgroup for its largest parts).
+    capacity and one workgroup size for all graphs (the batched launch sizes every workgroup for
+    its largest parts); apply the size with Batch.set_launch.
     """
     import torch
 

@@ -129,6 +129,9 @@ static int hip_status(hipError_t e, const char *what) {
   return fail(EPK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+extern "C" int epk_batch_set_launch(epk_batch *b, int32_t wg);
+static void size_batch_grids(epk_batch *b);
+
 // ------------------------------------------------------------------ batch merge
 
 template <typename T>
@@ -332,14 +335,30 @@ static int build_plans(const epk_graph *gs, int32_t n_graphs, int32_t cap, std::
 // capacity, run out of d_scratch: the median of 5 timings of 5 back-to-back
 // passes.  EPK_ERANGE if the batch does not fit in the scratch memory or in
 // LDS.  Also returns the batch's algorithmic bytes per pass.
-static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, void *d_scratch, size_t scratch_bytes,
-                      hipStream_t s, float *ms_out, int32_t *wg_out, int64_t *bytes_out) {
+// Workgroup sizes the autotuner tries at capacity cap, largest first (ties go
+// to the larger): multiples of 64 up to the pipelined kernels' 256 lanes, with
+// at most two edges per lane.
+static std::vector<int32_t> tune_wgs(int32_t cap) {
+  std::vector<int32_t> w;
+  for (int32_t wg : {256, 128, 64})
+    if (2 * wg >= cap) w.push_back(wg);
+  if (w.empty()) w.push_back(256);
+  return w;
+}
+
+// Times the batched forward + adjoint launch of all graphs at capacity cap,
+// once per workgroup size in wgs (median of 5 timings of 5 passes each):
+// ms_out[i] for wgs[i], 1e30 where that size cannot run.  The plans and the
+// merged image are built once per capacity.
+static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, const std::vector<int32_t> &wgs,
+                      void *d_scratch, size_t scratch_bytes, hipStream_t s, std::vector<float> &ms_out,
+                      int64_t *bytes_out) {
+  ms_out.assign(wgs.size(), 1e30f);
   std::vector<epk_plan *> plans;
   int st = build_plans(gs, n_graphs, cap, plans);
   if (st) return st;
   epk_batch *b = nullptr;
   st = epk_batch_create(n_graphs, plans.data(), &b);
-  const int32_t wg = plans[0]->wg;
   for (epk_plan *p : plans) epk_plan_destroy(p);
   if (st) return st;
   size_t img = 0, ws = 0;
@@ -362,32 +381,43 @@ static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, void *
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  std::vector<float> t;
   constexpr int kPasses = 5;
-  for (int it = 0; it < 6 && !st; ++it) {  // the first timing warms up
-    (void)hipEventRecord(e0, s);
-    for (int l = 0; l < kPasses && !st; ++l) {
-      st = epk_batch_forward(b, q, o, base + img, s);
-      if (!st) st = epk_batch_backward(b, q, g, o, base + img, s);
+  for (size_t w = 0; w < wgs.size() && !st; ++w) {
+    if (epk_batch_set_launch(b, wgs[w]) != EPK_OK) continue;  // not runnable at this capacity
+    std::vector<float> t;
+    for (int it = 0; it < 6 && !st; ++it) {  // the first timing warms up
+      (void)hipEventRecord(e0, s);
+      for (int l = 0; l < kPasses && !st; ++l) {
+        st = epk_batch_forward(b, q, o, base + img, s);
+        if (!st) st = epk_batch_backward(b, q, g, o, base + img, s);
+      }
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (it >= 1) t.push_back(ms / kPasses);
     }
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (it >= 1) t.push_back(ms / kPasses);
+    if (!st) {
+      std::sort(t.begin(), t.end());
+      ms_out[w] = t[t.size() / 2];
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (!st) {
-    std::sort(t.begin(), t.end());
-    *ms_out = t[t.size() / 2];
-    *wg_out = wg;
-    *bytes_out = b->bytes_fwd + b->bytes_bwd;
-  }
+  *bytes_out = b->bytes_fwd + b->bytes_bwd;
   epk_batch_destroy(b);
   return st;
 }
 
+
+// The batch's persistent grids: as many workgroups of b->wg lanes as fit on
+// the device's CUs (LDS, waves), at most one per work item.
+static void size_batch_grids(epk_batch *b) {
+  b->grid_fwd = pipe_grid(b->cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false, 4, false, int(b->max_cap)),
+                          b->k, false);
+  b->grid_bwd = pipe_grid(b->cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true, 4, false, int(b->max_cap)),
+                          b->k, false);
+}
 
 }  // namespace epk
 
@@ -565,13 +595,22 @@ int epk_batch_upload(epk_batch *b, void *d_image, void *stream) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_status(e, "CU count");
-  b->grid_fwd = pipe_grid(cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_fwd), false, 4, false, int(b->max_cap)),
-                          b->k, false);
-  b->grid_bwd = pipe_grid(cus, pipe_blocks_per_cu(int(b->wg), size_t(b->lds_bwd), true, 4, false, int(b->max_cap)),
-                          b->k, false);
+  b->cus = cus;
+  size_batch_grids(b);
   e = hipMemcpyAsync(d_image, b->image.data(), b->lay.total, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_status(e, "batch upload");
   b->d_image = d_image;
+  return EPK_OK;
+}
+
+int epk_batch_set_launch(epk_batch *b, int32_t wg) {
+  clear_error();
+  if (!b) return fail(EPK_EINVAL, "batch is NULL");
+  if (wg == 0) return EPK_OK;
+  if (wg < 64 || wg > 256 || wg % 64) return fail(EPK_EINVAL, "batch workgroup must be 64..256, multiple of 64");
+  if (b->max_cap > 8 * int64_t(wg)) return fail(EPK_EINVAL, "batch capacity exceeds 8 edges per lane");
+  b->wg = wg;
+  if (b->cus) size_batch_grids(b);
   return EPK_OK;
 }
 
@@ -654,23 +693,32 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
     // Timings within kTie of the fastest count as equal; among those the
     // fewest algorithmic bytes win, so that timing noise does not decide.
     constexpr float kTie = 1.02f;
-    std::vector<float> ms(size_t(n_caps), 1e30f);
-    std::vector<int32_t> wgs(size_t(n_caps), 0);
-    std::vector<int64_t> bytes(size_t(n_caps), 0);
+    struct Trial {
+      int32_t cap, wg;
+      float ms;
+      int64_t bytes;
+    };
+    std::vector<Trial> trials;
     float best = 1e30f;
     for (int32_t i = 0; i < n_caps; ++i) {
-      const int st = time_batch(gs, n_graphs, caps[i], d_scratch, scratch_bytes, s, &ms[i], &wgs[i], &bytes[i]);
+      const std::vector<int32_t> wgs = tune_wgs(caps[i]);
+      std::vector<float> ms;
+      int64_t bytes = 0;
+      const int st = time_batch(gs, n_graphs, caps[i], wgs, d_scratch, scratch_bytes, s, ms, &bytes);
       if (st == EPK_ERANGE) continue;  // capacity not runnable here
       if (st) return st;
-      best = std::min(best, ms[i]);
+      for (size_t w = 0; w < wgs.size(); ++w) {
+        trials.push_back({caps[i], wgs[w], ms[w], bytes});
+        best = std::min(best, ms[w]);
+      }
     }
     if (best >= 1e30f) return fail(EPK_ERANGE, "no capacity could be timed (scratch or LDS too small)");
     int64_t fewest = -1;
-    for (int32_t i = 0; i < n_caps; ++i)
-      if (ms[i] <= best * kTie && (fewest < 0 || bytes[i] < fewest)) {
-        fewest = bytes[i];
-        best_cap = caps[i];
-        best_wg = wgs[i];
+    for (const Trial &t : trials)  // in order: caps as listed, larger workgroups first
+      if (t.ms <= best * kTie && (fewest < 0 || t.bytes < fewest)) {
+        fewest = t.bytes;
+        best_cap = t.cap;
+        best_wg = t.wg;
       }
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);

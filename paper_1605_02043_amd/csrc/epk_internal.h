@@ -148,6 +148,7 @@ struct epk_batch {
   int64_t R = 0, n_heavy = 0, n_iso = 0, max_u = 0, max_nf = 0, max_cap = 0, wg = 256;
   bool vmajor = false;
   int64_t grid_fwd = 0, grid_bwd = 0;  // pipelined persistent grids
+  int32_t cus = 0;                     // compute units of the device uploaded to
   int64_t lds_fwd = 0, lds_bwd = 0, bytes_fwd = 0, bytes_bwd = 0;
   void *d_image = nullptr;
 };

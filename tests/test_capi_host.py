@@ -198,6 +198,30 @@ def test_layout_parity_spmv_and_isolated():
     _check_layout(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"], order="input")
 
 
+def test_batch_set_launch_validation():
+    """The batch's workgroup size: multiples of 64 up to 256 lanes, at most 8 edges per lane;
+    0 keeps the current size.  Host only (no upload)."""
+    from paper_1605_02043_amd.batch import Batch
+
+    graphs = gen.batch_graphs(4, seed=2, lo=200, hi=800)
+    plans = [Plan(g["edges"], g["n"], 512, g["geom"].astype(np.float32)) for g in graphs]
+    B = Batch(plans)
+    assert B.info()["wg"] == 256
+    for bad in (32, 96, 320, 1024):
+        with pytest.raises(_lib.EpkError) as e:
+            B.set_launch(bad)
+        assert e.value.status == _lib.EPK_EINVAL
+        assert B.info()["wg"] == 256
+    B.set_launch(64)  # 512 edges = 8 per lane
+    assert B.info()["wg"] == 64
+    B.set_launch(0)
+    assert B.info()["wg"] == 64
+    B2 = Batch([Plan(g["edges"], g["n"], 576, g["geom"].astype(np.float32)) for g in graphs])
+    with pytest.raises(_lib.EpkError) as e:
+        B2.set_launch(64)  # 9 or more edges per lane
+    assert e.value.status == _lib.EPK_EINVAL
+
+
 def test_plan_handles_empty_graph():
     P = Plan(np.zeros((0, 2), np.int32), 5, 16, np.zeros((0, 4), np.float32))
     assert P.stats["n_parts"] == 0 and P.stats["loads"] == 0

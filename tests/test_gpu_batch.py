@@ -66,6 +66,21 @@ def test_batch_small_mixed_caps():
     _check(graphs, plans, B, "batch12")
 
 
+def test_batch_launch_shapes_bitwise():
+    """The workgroup size of the persistent launch changes lanes per edge, never a result bit."""
+    graphs = gen.batch_graphs(12, seed=5, lo=200, hi=4000)
+    for cap, shapes in ((256, (128,)), (128, (64, 256))):
+        say(f"case batch12 cap {cap} launch shapes {shapes}")
+        plans, B = _build(graphs, [cap] * len(graphs))
+        qd, gd = _check(graphs, plans, B, f"batch12/cap{cap}")
+        r0, g0 = B.forward(qd).clone(), B.backward(qd, gd).clone()
+        for wg in shapes:
+            B.set_launch(wg)
+            say(f"  wg {wg}: {B.info()}")
+            assert B.info()["wg"] == wg
+            assert torch.equal(B.forward(qd), r0) and torch.equal(B.backward(qd, gd), g0)
+
+
 def test_batch256_and_graph_replay():
     graphs = gen.batch_graphs(256, seed=0)
     caps = [256] * len(graphs)
@@ -149,9 +164,12 @@ def test_autotune_picks_listed_caps(tmp_path):
     say("case autotune")
     cache = str(tmp_path / "tune.txt")
     caps, wgs = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)
+    say(f"  chose cap {caps[0]} wg {wgs[0]}")
     assert set(caps.tolist()) <= {64, 128, 256, 512}
-    assert (wgs >= 64).all()
-    caps2, _ = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)  # from the cache
-    assert np.array_equal(caps, caps2)
+    assert len(set(caps.tolist())) == 1 and len(set(wgs.tolist())) == 1
+    assert wgs[0] in (64, 128, 256) and 2 * wgs[0] >= caps[0]
+    caps2, wgs2 = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)  # from the cache
+    assert np.array_equal(caps, caps2) and np.array_equal(wgs, wgs2)
     plans, B = _build(graphs, caps)
+    B.set_launch(int(wgs[0]))
     _check(graphs, plans, B, "tuned")
