@@ -315,7 +315,7 @@ def main():
     GRAPH_TIMING = not args.eager
     COLD_STEPS = args.cold_steps
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import torch
