@@ -613,11 +613,11 @@ def bench_batch(args, torch):
     m = sum(len(g["edges"]) for g in graphs)
     n = sum(g["n"] for g in graphs)
     t0 = time.perf_counter()
-    caps, wgs = autotune(graphs, caps=(64, 128, 256, 512))
+    caps, wgs, directs = autotune(graphs, caps=(64, 128, 256, 512))
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     plans = [Plan(g["edges"], g["n"], int(c), g["geom"].astype(np.float32)) for g, c in zip(graphs, caps)]
-    B = Batch(plans).set_launch(int(wgs[0])).upload("cuda")
+    B = Batch(plans).set_launch(int(wgs[0]), int(directs[0])).upload("cuda")
     plan_s = time.perf_counter() - t0
     q = torch.from_numpy(np.concatenate([gen.flux_state(g["n"], seed=i)[p.perm()] for i, (g, p) in
                                          enumerate(zip(graphs, plans))])).cuda()
@@ -658,15 +658,17 @@ def bench_batch(args, torch):
     info = B.info()
     algo = info["bytes_fwd"] + info["bytes_bwd"]
     ach = algo / (gpu_ms * 1e-3) / 1e9
-    out = _common(args, "edges/s, batched persistent FLUX5 fwd+bwd over 256 uneven meshes, HIP-graph replay, 1 MI355X",
+    out = _common(args, "edges/s, batched FLUX5 fwd+bwd over 256 uneven meshes in one launch per pass, HIP-graph replay, 1 MI355X",
                   m / wall, wall * 1e3,
                   {"workload": f"batch256: 256 2D/3D mesh graphs, vertex counts log-uniform in [1024, 65536], "
-                               f"total n={n}, m={m}, one capacity and workgroup size autotuned over {{64, 128, 256, 512}} x {{64, 128, 256}} lanes by timing the batched launch",
+                               f"total n={n}, m={m}, one capacity and launch shape autotuned over {{64, 128, 256, 512}} x {{64, 128, 256}} lanes x {{one workgroup per item, pipelined persistent}} by timing the batched launch",
                                "graphs": 256, "timing": "the timed steps captured in one HIP graph, one replay"})
-    out["roofline"] = {"bound": "hbm", "kernel": "graph replay (persistent fwd + reduce + persistent bwd + reduce)",
+    kind = "one workgroup per item" if info["direct"] else "pipelined persistent"
+    out["roofline"] = {"bound": "hbm", "kernel": f"graph replay (fwd + reduce + bwd + reduce, {kind})",
                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                        "traffic": None}
-    out["batch"] = {"items": info["items"], "grid": info["grid"], "wg": info["wg"], "lds_fwd": info["lds_fwd"],
+    out["batch"] = {"items": info["items"], "launch": kind, "grid": info["items"] if info["direct"] else info["grid"],
+                    "wg": info["wg"], "lds_fwd": info["lds_fwd"],
                     "caps": {int(c): int((caps == c).sum()) for c in np.unique(caps)}, "gpu_ms_per_step": gpu_ms,
                     "algorithmic_bytes_per_step": algo, "gen_s": gen_s, "autotune_s": tune_s, "plan_s": plan_s}
     out["source_sha256"] = source_sha256()

@@ -267,41 +267,49 @@ int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out);
 int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes);
 /* Copy the image to d_image and size the grids for the current device.   */
 int epk_batch_upload(epk_batch *b, void *d_image, void *stream);
-/* Workgroup size of the batch's persistent launch: wg lanes (64..256,
- * multiple of 64, at least capacity / 8; 0 keeps the current one).  The
- * grids follow at once if the batch is uploaded, else at upload.  Results
- * do not depend on wg (the per-vertex sums run in a fixed order).  Host
- * only; EPK_EINVAL for a size out of range.                               */
-int epk_batch_set_launch(epk_batch *b, int32_t wg);
+/* Launch shape of the batch.  wg: workgroup size (64..256, multiple of 64,
+ * at least capacity / 8; 0 keeps the current one).  direct: 1 runs one
+ * workgroup per (graph, part) item, as the single-plan kernels do (needs one
+ * capacity for all graphs, else EPK_ESTATE); 0 the pipelined persistent
+ * launch (the default); -1 keeps the current kind.  The grids follow at once
+ * if the batch is uploaded, else at upload.  Results do not depend on the
+ * shape (the per-vertex sums run in a fixed order).  Host only; EPK_EINVAL
+ * for a size out of range.                                                */
+int epk_batch_set_launch(epk_batch *b, int32_t wg, int32_t direct);
 /* vertex_offset[n_graphs + 1] (rows), total in [n_graphs].               */
 int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset);
 /* [0] items, [1] forward grid, [2] forward LDS bytes, [3] / [4] algorithmic
  * bytes of one forward / adjoint, [5] workgroup size, [6] edges,
- * [7] adjoint grid.                                                       */
+ * [7] adjoint grid (the pipelined launch's grids), [8] one workgroup per
+ * item (1) or pipelined (0), [9] whether one workgroup per item is
+ * possible for this batch.                                                */
 int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info);
 int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream);
 int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws,
                        void *stream);
 void epk_batch_destroy(epk_batch *b);
 
-/* Capacity and workgroup selection for a batch (the block-size study of
+/* Capacity and launch-shape selection for a batch (the block-size study of
  * Section 5.2, done by measurement): for each capacity in caps[n_caps],
  * build every graph's EP plan at that capacity, merge them into one batch
- * and time its pipelined forward + adjoint launch (median of 5 timings of 5
- * passes) at each workgroup size of 256, 128 and 64 lanes that leaves at
- * most two edges per lane.  The fastest pair is chosen for all graphs,
- * since a batched launch sizes every workgroup's LDS for its largest parts.
+ * and time its forward + adjoint launch (median of 5 timings of 5 passes)
+ * in each launch shape: one workgroup per item and the pipelined persistent
+ * launch, each at 256, 128 and 64 lanes where that leaves at most two edges
+ * per lane.  The fastest (capacity, shape) is chosen for all graphs, since a
+ * batched launch sizes every workgroup's LDS for its largest parts.
  * Timings within 2% of the fastest count as ties, won by the fewest
- * algorithmic bytes, then by the capacity listed first and the larger
- * workgroup.  Results are cached in cache_path (a text file of key|cap wg
- * lines, NULL = no cache).  d_scratch (scratch_bytes) is caller-allocated
- * device memory for the trials (a whole batch's image, workspace and three
- * state arrays); a capacity that does not fit is skipped, EPK_ERANGE if
- * none fits.  Plans are built on up to 16 host threads.  Synchronises the
- * stream.  chosen_cap[n_graphs] out; chosen_wg[n_graphs] may be NULL.   */
+ * algorithmic bytes, then by the capacity listed first, one workgroup per
+ * item and the larger workgroup.  Results are cached in cache_path (a text
+ * file of key|cap wg direct lines, NULL = no cache).  d_scratch
+ * (scratch_bytes) is caller-allocated device memory for the trials (a whole
+ * batch's image, workspace and three state arrays); a capacity that does
+ * not fit is skipped, EPK_ERANGE if none fits.  Plans are built on up to 16
+ * host threads.  Synchronises the stream.  chosen_cap[n_graphs] out;
+ * chosen_wg[n_graphs] and chosen_direct[n_graphs] (1: one workgroup per
+ * item, 0: pipelined; see epk_batch_set_launch) may be NULL.              */
 int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps,
                  const char *cache_path, void *d_scratch, size_t scratch_bytes, void *stream,
-                 int32_t *chosen_cap, int32_t *chosen_wg);
+                 int32_t *chosen_cap, int32_t *chosen_wg, int32_t *chosen_direct);
 
 const char *epk_last_error(void);
 const char *epk_version(void);

@@ -69,14 +69,14 @@ _SIGS = {
     "epk_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
     "epk_batch_device_bytes": (C.c_int, [_P, _SZP, _SZP]),
     "epk_batch_upload": (C.c_int, [_P, _P, _P]),
-    "epk_batch_set_launch": (C.c_int, [_P, C.c_int32]),
+    "epk_batch_set_launch": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "epk_batch_vertex_offsets": (C.c_int, [_P, _I64P]),
     "epk_batch_info": (C.c_int, [_P, _I64P, C.c_int32]),
     "epk_batch_forward": (C.c_int, [_P, _FP, _FP, _P, _P]),
     "epk_batch_backward": (C.c_int, [_P, _FP, _FP, _FP, _P, _P]),
     "epk_batch_destroy": (None, [_P]),
     "epk_autotune": (C.c_int, [C.POINTER(Graph), C.c_int32, _I32P, C.c_int32, C.c_char_p, _P, C.c_size_t, _P,
-                               _I32P, _I32P]),
+                               _I32P, _I32P, _I32P]),
     "epk_adaptive_start": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_double, C.POINTER(_P)]),
     "epk_adaptive_poll": (C.c_int, [_P, _I32P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "epk_adaptive_take": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),

@@ -41,13 +41,15 @@ class Batch:
         return a.value, b.value
 
     def info(self) -> dict:
-        a = np.zeros(8, dtype=np.int64)
-        check(lib.epk_batch_info(self._h, i64p(a), 8))
-        return dict(zip(["items", "grid", "lds_fwd", "bytes_fwd", "bytes_bwd", "wg", "m", "grid_bwd"], a.tolist()))
+        a = np.zeros(10, dtype=np.int64)
+        check(lib.epk_batch_info(self._h, i64p(a), 10))
+        return dict(zip(["items", "grid", "lds_fwd", "bytes_fwd", "bytes_bwd", "wg", "m", "grid_bwd", "direct",
+                         "direct_ok"], a.tolist()))
 
-    def set_launch(self, wg: int):
-        """Workgroup size of the persistent launch (64..256, multiple of 64; 0 keeps it)."""
-        check(lib.epk_batch_set_launch(self._h, int(wg)))
+    def set_launch(self, wg: int = 0, direct: int = -1):
+        """Launch shape: workgroup size (64..256, multiple of 64; 0 keeps it) and launch kind
+        (direct=1: one workgroup per (graph, part) item; 0: pipelined persistent; -1 keeps it)."""
+        check(lib.epk_batch_set_launch(self._h, int(wg), int(direct)))
         return self
 
     def upload(self, device="cuda"):
@@ -79,12 +81,13 @@ class Batch:
 
 
 def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", scratch_bytes=None):
-    """Pick the batch's capacity and workgroup size by timing the batched forward + adjoint
-    launch at each candidate pair.
+    """Pick the batch's capacity and launch shape by timing the batched forward + adjoint launch
+    at each candidate.
 
-    graphs: list of dicts with 'edges', 'n', 'geom'.  Returns (caps[n_graphs], wgs[n_graphs]), one
-    capacity and one workgroup size for all graphs (the batched launch sizes every workgroup for
-    its largest parts); apply the size with Batch.set_launch.
+    graphs: list of dicts with 'edges', 'n', 'geom'.  Returns (caps, wgs, directs), each
+    [n_graphs]: one capacity, one workgroup size and one launch kind (1: one workgroup per item,
+    0: pipelined persistent) for all graphs (the batched launch sizes every workgroup for its
+    largest parts); apply the shape with Batch.set_launch(wgs[0], directs[0]).
     """
     import torch
 
@@ -100,11 +103,12 @@ def autotune(graphs, caps=(64, 128, 256, 512), cache_path=None, device="cuda", s
     c = np.asarray(caps, dtype=np.int32)
     out_cap = np.zeros(len(graphs), dtype=np.int32)
     out_wg = np.zeros(len(graphs), dtype=np.int32)
+    out_direct = np.zeros(len(graphs), dtype=np.int32)
     check(lib.epk_autotune(arr, len(graphs), i32p(c), len(c), cache_path.encode() if cache_path else None,
                            _dptr(scratch), scratch.numel(), _stream_handle(torch, _full_device(torch, device)),
-                           i32p(out_cap), i32p(out_wg)))
+                           i32p(out_cap), i32p(out_wg), i32p(out_direct)))
     del keep
-    return out_cap, out_wg
+    return out_cap, out_wg, out_direct
 
 
 __all__ = ["Batch", "autotune", "Plan"]

@@ -116,6 +116,15 @@ DevPlan dev_batch(const epk_batch *bt) {
   return P;
 }
 
+// The batch as the direct kernels see it: headers in item order and the
+// padded foreign ids.
+static DevPlan dev_batch_direct(const epk_batch *bt) {
+  DevPlan P = dev_batch(bt);
+  P.hdr = dptr<int32_t>(bt->d_image, bt->lay.hdr_items);
+  P.pfid = dptr<int32_t>(bt->d_image, bt->lay.pfid);
+  return P;
+}
+
 // Grid of a pipelined launch: per_cu workgroups on each of cus CUs, at most
 // one per part, a multiple of 8 under the XCD-aware part lists.
 static int64_t pipe_grid(int cus, int per_cu, int64_t k, bool swizzle) {
@@ -129,7 +138,7 @@ static int hip_status(hipError_t e, const char *what) {
   return fail(EPK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-extern "C" int epk_batch_set_launch(epk_batch *b, int32_t wg);
+extern "C" int epk_batch_set_launch(epk_batch *b, int32_t wg, int32_t direct);
 static void size_batch_grids(epk_batch *b);
 
 // ------------------------------------------------------------------ batch merge
@@ -218,6 +227,28 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
     delete B;
     return fail(EPK_ERANGE, "batch too large for 32-bit ids");
   }
+  // The direct launch (one workgroup per item) finds item i's edge records at
+  // i * cap and its foreign ids at i * max_nf before its header arrives, as
+  // for a single plan: possible when every plan has the same capacity.
+  B->direct_ok = true;
+  for (int32_t g = 0; g < n_graphs; ++g)
+    if (plans[g]->cap != plans[0]->cap || plans[g]->me != int64_t(plans[g]->k) * plans[g]->cap)
+      B->direct_ok = false;
+  std::vector<int32_t> hdr_items, pfid;
+  if (B->direct_ok) {
+    hdr_items = hdr;
+    pfid.assign(size_t(B->k * std::max<int64_t>(B->max_nf, 1)), -1);
+    int64_t item = 0;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+      const epk_plan *p = plans[g];
+      const int32_t *src = hptr<int32_t>(p, p->lay.pfid);
+      for (int64_t q = 0; q < p->k; ++q, ++item)
+        for (int64_t j = 0; j < p->max_nf; ++j) {
+          const int32_t v = src[q * p->max_nf + j];
+          pfid[size_t(item * B->max_nf + j)] = v < 0 ? -1 : int32_t(v + B->voff[g]);
+        }
+    }
+  }
   // headers in processing order: largest parts first (ties: lower id first);
   // the pipelined kernel deals them round-robin over its workgroups
   {
@@ -234,6 +265,9 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   B->wg = std::min<int64_t>(256, std::max<int64_t>(64, ((B->max_cap + 63) / 64) * 64));
   B->lds_fwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, false, false, B->vmajor);
   B->lds_bwd = flux_pipe_lds(B->max_u, B->max_nf, B->max_cap, true, false, B->vmajor);
+  B->lds_fwd_direct = flux_fwd_lds(B->max_u, B->max_nf, B->max_cap, B->vmajor);
+  B->lds_bwd_direct = flux_bwd_lds(B->max_u, B->max_nf, B->max_cap, B->vmajor);
+  if (B->lds_fwd_direct > kMaxLdsBytes || B->lds_bwd_direct > kMaxLdsBytes) B->direct_ok = false;
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");
@@ -259,6 +293,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   L.rrec = take(rrec.size() * 4);
   L.heavy = take(heavy.size() * 4);
   L.iso = take(iso.size() * 4);
+  L.hdr_items = take(hdr_items.size() * 4);
+  L.pfid = take(pfid.size() * 4);
   L.total = off;
   B->image.assign(L.total, 0);
   auto put = [&](size_t o, const void *src, size_t bytes) {
@@ -277,6 +313,8 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   put(L.rrec, rrec.data(), rrec.size() * 4);
   put(L.heavy, heavy.data(), heavy.size() * 4);
   put(L.iso, iso.data(), iso.size() * 4);
+  put(L.hdr_items, hdr_items.data(), hdr_items.size() * 4);
+  put(L.pfid, pfid.data(), pfid.size() * 4);
   B->ws_bytes = align256(std::max<size_t>(size_t(foff) * 5 * 4, 4));
   *out = B;
   return EPK_OK;
@@ -347,13 +385,18 @@ static std::vector<int32_t> tune_wgs(int32_t cap) {
 }
 
 // Times the batched forward + adjoint launch of all graphs at capacity cap,
-// once per workgroup size in wgs (median of 5 timings of 5 passes each):
-// ms_out[i] for wgs[i], 1e30 where that size cannot run.  The plans and the
-// merged image are built once per capacity.
-static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, const std::vector<int32_t> &wgs,
+// once per launch shape (workgroup size, one workgroup per item or
+// pipelined) in shapes (median of 5 timings of 5 passes each): ms_out[i] for
+// shapes[i], 1e30 where that shape cannot run.  The plans and the merged
+// image are built once per capacity.
+struct LaunchShape {
+  int32_t wg, direct;
+};
+
+static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, const std::vector<LaunchShape> &shapes,
                       void *d_scratch, size_t scratch_bytes, hipStream_t s, std::vector<float> &ms_out,
                       int64_t *bytes_out) {
-  ms_out.assign(wgs.size(), 1e30f);
+  ms_out.assign(shapes.size(), 1e30f);
   std::vector<epk_plan *> plans;
   int st = build_plans(gs, n_graphs, cap, plans);
   if (st) return st;
@@ -382,8 +425,10 @@ static int time_batch(const epk_graph *gs, int32_t n_graphs, int32_t cap, const 
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   constexpr int kPasses = 5;
-  for (size_t w = 0; w < wgs.size() && !st; ++w) {
-    if (epk_batch_set_launch(b, wgs[w]) != EPK_OK) continue;  // not runnable at this capacity
+  for (size_t w = 0; w < shapes.size() && !st; ++w) {
+    // a shape this batch cannot run (capacity too large for the lanes, or
+    // mixed capacities for one workgroup per item) is skipped
+    if (epk_batch_set_launch(b, shapes[w].wg, shapes[w].direct) != EPK_OK) continue;
     std::vector<float> t;
     for (int it = 0; it < 6 && !st; ++it) {  // the first timing warms up
       (void)hipEventRecord(e0, s);
@@ -603,13 +648,18 @@ int epk_batch_upload(epk_batch *b, void *d_image, void *stream) {
   return EPK_OK;
 }
 
-int epk_batch_set_launch(epk_batch *b, int32_t wg) {
+int epk_batch_set_launch(epk_batch *b, int32_t wg, int32_t direct) {
   clear_error();
   if (!b) return fail(EPK_EINVAL, "batch is NULL");
-  if (wg == 0) return EPK_OK;
-  if (wg < 64 || wg > 256 || wg % 64) return fail(EPK_EINVAL, "batch workgroup must be 64..256, multiple of 64");
-  if (b->max_cap > 8 * int64_t(wg)) return fail(EPK_EINVAL, "batch capacity exceeds 8 edges per lane");
-  b->wg = wg;
+  if (direct < -1 || direct > 1) return fail(EPK_EINVAL, "direct must be -1, 0 or 1");
+  if (wg != 0) {
+    if (wg < 64 || wg > 256 || wg % 64) return fail(EPK_EINVAL, "batch workgroup must be 64..256, multiple of 64");
+    if (b->max_cap > 8 * int64_t(wg)) return fail(EPK_EINVAL, "batch capacity exceeds 8 edges per lane");
+  }
+  if (direct == 1 && !b->direct_ok)
+    return fail(EPK_ESTATE, "one workgroup per item needs one capacity for all graphs (and LDS for the largest part)");
+  if (wg != 0) b->wg = wg;
+  if (direct >= 0) b->direct = direct == 1;
   if (b->cus) size_batch_grids(b);
   return EPK_OK;
 }
@@ -624,8 +674,9 @@ int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset) {
 int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info) {
   clear_error();
   if (!b || !info) return fail(EPK_EINVAL, "NULL argument");
-  const int64_t v[8] = {b->k, b->grid_fwd, b->lds_fwd, b->bytes_fwd, b->bytes_bwd, b->wg, b->m, b->grid_bwd};
-  for (int32_t i = 0; i < n_info && i < 8; ++i) info[i] = v[i];
+  const int64_t v[10] = {b->k,  b->grid_fwd, b->lds_fwd,  b->bytes_fwd,  b->bytes_bwd,
+                         b->wg, b->m,        b->grid_bwd, int64_t(b->direct), int64_t(b->direct_ok)};
+  for (int32_t i = 0; i < n_info && i < 10; ++i) info[i] = v[i];
   return EPK_OK;
 }
 
@@ -636,8 +687,10 @@ int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, 
   if (b->n > 0 && (!q || !r || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
   const DevPlan P = dev_batch(b);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_pipe(P, int(b->wg), int(b->grid_fwd), size_t(b->lds_fwd), q, nullptr, r, nullptr, 0.f,
-                                  static_cast<float *>(d_ws), false, 0, s);
+  hipError_t e = b->direct ? launch_flux_fwd(dev_batch_direct(b), int(b->wg), size_t(b->lds_fwd_direct), q, r,
+                                             nullptr, 0.f, static_cast<float *>(d_ws), 1, s)
+                           : launch_flux_pipe(P, int(b->wg), int(b->grid_fwd), size_t(b->lds_fwd), q, nullptr, r,
+                                              nullptr, 0.f, static_cast<float *>(d_ws), false, 0, s);
   if (e != hipSuccess) return hip_status(e, "batch forward launch");
   return hip_status(launch_reduce(P, 5, r, static_cast<const float *>(d_ws), q, nullptr, 0.f, s), "reduce launch");
 }
@@ -649,8 +702,10 @@ int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, flo
   if (b->n > 0 && (!q || !g_r || !g_q || !d_ws)) return fail(EPK_EINVAL, "NULL argument");
   const DevPlan P = dev_batch(b);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_flux_pipe(P, int(b->wg), int(b->grid_bwd), size_t(b->lds_bwd), q, g_r, g_q, nullptr, 0.f,
-                                  static_cast<float *>(d_ws), true, 0, s);
+  hipError_t e = b->direct ? launch_flux_bwd(dev_batch_direct(b), int(b->wg), size_t(b->lds_bwd_direct), q, g_r, g_q,
+                                             static_cast<float *>(d_ws), 1, s)
+                           : launch_flux_pipe(P, int(b->wg), int(b->grid_bwd), size_t(b->lds_bwd), q, g_r, g_q,
+                                              nullptr, 0.f, static_cast<float *>(d_ws), true, 0, s);
   if (e != hipSuccess) return hip_status(e, "batch adjoint launch");
   return hip_status(launch_reduce(P, 5, g_q, static_cast<const float *>(d_ws), nullptr, nullptr, 0.f, s),
                     "reduce launch");
@@ -659,7 +714,8 @@ int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, flo
 void epk_batch_destroy(epk_batch *b) { delete b; }
 
 int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int32_t n_caps, const char *cache_path,
-                 void *d_scratch, size_t scratch_bytes, void *stream, int32_t *chosen_cap, int32_t *chosen_wg) {
+                 void *d_scratch, size_t scratch_bytes, void *stream, int32_t *chosen_cap, int32_t *chosen_wg,
+                 int32_t *chosen_direct) {
   clear_error();
   if (!gs || n_graphs < 1 || !caps || n_caps < 1 || !chosen_cap) return fail(EPK_EINVAL, "bad arguments");
   if (!d_scratch) return fail(EPK_EINVAL, "d_scratch is NULL");
@@ -672,7 +728,7 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::string key = tune_key(gs, n_graphs, caps, n_caps);
-  int32_t best_cap = 0, best_wg = 0;
+  int32_t best_cap = 0, best_wg = 0, best_direct = 0;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -680,10 +736,12 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
       const size_t bar = line.find('|');
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
       std::istringstream rest(line.substr(bar + 1));
-      int32_t c = 0, w = 0;
+      int32_t c = 0, w = 0, d = 0;
       if (rest >> c >> w) {
+        if (!(rest >> d)) d = 0;  // lines written before the launch kind was tuned
         best_cap = c;
         best_wg = w;
+        best_direct = d;
       }
     }
   }
@@ -694,41 +752,46 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
     // fewest algorithmic bytes win, so that timing noise does not decide.
     constexpr float kTie = 1.02f;
     struct Trial {
-      int32_t cap, wg;
+      int32_t cap;
+      LaunchShape shape;
       float ms;
       int64_t bytes;
     };
     std::vector<Trial> trials;
     float best = 1e30f;
     for (int32_t i = 0; i < n_caps; ++i) {
-      const std::vector<int32_t> wgs = tune_wgs(caps[i]);
+      std::vector<LaunchShape> shapes;  // one workgroup per item first, then pipelined; larger workgroups first
+      for (int32_t direct : {1, 0})
+        for (int32_t wg : tune_wgs(caps[i])) shapes.push_back({wg, direct});
       std::vector<float> ms;
       int64_t bytes = 0;
-      const int st = time_batch(gs, n_graphs, caps[i], wgs, d_scratch, scratch_bytes, s, ms, &bytes);
+      const int st = time_batch(gs, n_graphs, caps[i], shapes, d_scratch, scratch_bytes, s, ms, &bytes);
       if (st == EPK_ERANGE) continue;  // capacity not runnable here
       if (st) return st;
-      for (size_t w = 0; w < wgs.size(); ++w) {
-        trials.push_back({caps[i], wgs[w], ms[w], bytes});
+      for (size_t w = 0; w < shapes.size(); ++w) {
+        trials.push_back({caps[i], shapes[w], ms[w], bytes});
         best = std::min(best, ms[w]);
       }
     }
     if (best >= 1e30f) return fail(EPK_ERANGE, "no capacity could be timed (scratch or LDS too small)");
     int64_t fewest = -1;
-    for (const Trial &t : trials)  // in order: caps as listed, larger workgroups first
+    for (const Trial &t : trials)  // in trial order: caps as listed, then the shapes' order
       if (t.ms <= best * kTie && (fewest < 0 || t.bytes < fewest)) {
         fewest = t.bytes;
         best_cap = t.cap;
-        best_wg = t.wg;
+        best_wg = t.shape.wg;
+        best_direct = t.shape.direct;
       }
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);
-      outf << key << '|' << best_cap << ' ' << best_wg << '\n';
+      outf << key << '|' << best_cap << ' ' << best_wg << ' ' << best_direct << '\n';
     }
   }
   clear_error();
   for (int32_t g = 0; g < n_graphs; ++g) {
     chosen_cap[g] = best_cap;
     if (chosen_wg) chosen_wg[g] = best_wg;
+    if (chosen_direct) chosen_direct[g] = best_direct;
   }
   return EPK_OK;
 }

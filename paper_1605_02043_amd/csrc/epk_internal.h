@@ -59,6 +59,7 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
 // Offsets (bytes) of the arrays inside a plan's device image.
 struct ImageLayout {
   size_t hdr = 0, eloc = 0, geom = 0, inc = 0, loff = 0, fid = 0, pfid = 0;
+  size_t hdr_items = 0;  // batch: headers in item order (the direct launch), next to the dealt order in hdr
   size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, rrec = 0, heavy = 0, iso = 0, eoff = 0;
   // SpMV adjoint: x incidence per part, y foreign ids, x-class reduction tables
   size_t xinc = 0, xlo = 0, xlofs = 0, rfid = 0, eid = 0, xrvid = 0, xroff = 0, xsidx = 0, xrslot = 0, xheavy = 0;
@@ -149,6 +150,10 @@ struct epk_batch {
   bool vmajor = false;
   int64_t grid_fwd = 0, grid_bwd = 0;  // pipelined persistent grids
   int32_t cus = 0;                     // compute units of the device uploaded to
+  // one workgroup per item (all plans share one capacity, so item i's edge
+  // records start at i * cap and its padded foreign ids at i * max_nf)
+  bool direct_ok = false, direct = false;
+  int64_t lds_fwd_direct = 0, lds_bwd_direct = 0;
   int64_t lds_fwd = 0, lds_bwd = 0, bytes_fwd = 0, bytes_bwd = 0;
   void *d_image = nullptr;
 };

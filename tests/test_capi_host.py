@@ -220,6 +220,22 @@ def test_batch_set_launch_validation():
     with pytest.raises(_lib.EpkError) as e:
         B2.set_launch(64)  # 9 or more edges per lane
     assert e.value.status == _lib.EPK_EINVAL
+    # one workgroup per item: needs one capacity for every graph
+    assert B.info()["direct_ok"] == 1 and B.info()["direct"] == 0
+    B.set_launch(0, 1)
+    assert B.info()["direct"] == 1 and B.info()["wg"] == 64
+    B.set_launch(256, -1)
+    assert B.info()["direct"] == 1 and B.info()["wg"] == 256
+    with pytest.raises(_lib.EpkError) as e:
+        B.set_launch(0, 2)
+    assert e.value.status == _lib.EPK_EINVAL
+    B.set_launch(0, 0)
+    assert B.info()["direct"] == 0
+    B3 = Batch([Plan(g["edges"], g["n"], c, g["geom"].astype(np.float32)) for g, c in zip(graphs, (128, 256, 128, 256))])
+    assert B3.info()["direct_ok"] == 0
+    with pytest.raises(_lib.EpkError) as e:
+        B3.set_launch(0, 1)
+    assert e.value.status == _lib.EPK_ESTATE and B3.info()["direct"] == 0
 
 
 def test_plan_handles_empty_graph():

@@ -67,17 +67,18 @@ def test_batch_small_mixed_caps():
 
 
 def test_batch_launch_shapes_bitwise():
-    """The workgroup size of the persistent launch changes lanes per edge, never a result bit."""
+    """The launch shape (workgroup size; pipelined persistent or one workgroup per item) changes
+    lanes per edge and the order parts run in, never a result bit."""
     graphs = gen.batch_graphs(12, seed=5, lo=200, hi=4000)
-    for cap, shapes in ((256, (128,)), (128, (64, 256))):
+    for cap, shapes in ((256, ((128, 0), (256, 1), (128, 1))), (128, ((64, 0), (256, 0), (128, 1), (64, 1)))):
         say(f"case batch12 cap {cap} launch shapes {shapes}")
         plans, B = _build(graphs, [cap] * len(graphs))
         qd, gd = _check(graphs, plans, B, f"batch12/cap{cap}")
         r0, g0 = B.forward(qd).clone(), B.backward(qd, gd).clone()
-        for wg in shapes:
-            B.set_launch(wg)
-            say(f"  wg {wg}: {B.info()}")
-            assert B.info()["wg"] == wg
+        for wg, direct in shapes:
+            B.set_launch(wg, direct)
+            say(f"  wg {wg} direct {direct}: {B.info()}")
+            assert B.info()["wg"] == wg and B.info()["direct"] == direct
             assert torch.equal(B.forward(qd), r0) and torch.equal(B.backward(qd, gd), g0)
 
 
@@ -163,13 +164,13 @@ def test_autotune_picks_listed_caps(tmp_path):
     graphs = gen.batch_graphs(20, seed=1, lo=1024, hi=16384)
     say("case autotune")
     cache = str(tmp_path / "tune.txt")
-    caps, wgs = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)
-    say(f"  chose cap {caps[0]} wg {wgs[0]}")
+    caps, wgs, directs = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)
+    say(f"  chose cap {caps[0]} wg {wgs[0]} direct {directs[0]}")
     assert set(caps.tolist()) <= {64, 128, 256, 512}
-    assert len(set(caps.tolist())) == 1 and len(set(wgs.tolist())) == 1
-    assert wgs[0] in (64, 128, 256) and 2 * wgs[0] >= caps[0]
-    caps2, wgs2 = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)  # from the cache
-    assert np.array_equal(caps, caps2) and np.array_equal(wgs, wgs2)
+    assert len(set(caps.tolist())) == 1 and len(set(wgs.tolist())) == 1 and len(set(directs.tolist())) == 1
+    assert wgs[0] in (64, 128, 256) and 2 * wgs[0] >= caps[0] and directs[0] in (0, 1)
+    caps2, wgs2, directs2 = autotune(graphs, caps=(64, 128, 256, 512), cache_path=cache)  # from the cache
+    assert np.array_equal(caps, caps2) and np.array_equal(wgs, wgs2) and np.array_equal(directs, directs2)
     plans, B = _build(graphs, caps)
-    B.set_launch(int(wgs[0]))
+    B.set_launch(int(wgs[0]), int(directs[0]))
     _check(graphs, plans, B, "tuned")
