@@ -256,13 +256,14 @@ void epk_adaptive_destroy(epk_adaptive *a);
 
 /* --------------------------------------------------------------- batched */
 
-/* Many FLUX5 graphs in one persistent launch.  States of graph g live at
+/* Many FLUX5 graphs in one launch per pass.  States of graph g live at
  * rows [vertex_offset(g), vertex_offset(g) + n_g) of one [sum n][5] array,
  * in graph g's packed order.  The plans must be FLUX5 with 4 geometry
  * components; the batch copies what it needs, the plans may be destroyed.
- * Work items (graph, part) are dealt round-robin, largest first, to the
- * workgroups of one pipelined persistent launch (see
- * epk_plan_set_pipeline); the grid is fixed at upload.                    */
+ * Work items (graph, part) run one workgroup each when every plan has the
+ * same capacity, else they are dealt round-robin, largest first, to the
+ * workgroups of one pipelined persistent launch (see epk_plan_set_pipeline;
+ * epk_batch_set_launch picks either).                                     */
 int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out);
 int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes);
 /* Copy the image to d_image and size the grids for the current device.   */
@@ -270,8 +271,9 @@ int epk_batch_upload(epk_batch *b, void *d_image, void *stream);
 /* Launch shape of the batch.  wg: workgroup size (64..256, multiple of 64,
  * at least capacity / 8; 0 keeps the current one).  direct: 1 runs one
  * workgroup per (graph, part) item, as the single-plan kernels do (needs one
- * capacity for all graphs, else EPK_ESTATE); 0 the pipelined persistent
- * launch (the default); -1 keeps the current kind.  The grids follow at once
+ * capacity for all graphs, else EPK_ESTATE; the default where possible); 0
+ * the pipelined persistent launch (the default for mixed capacities); -1
+ * keeps the current kind.  The grids follow at once
  * if the batch is uploaded, else at upload.  Results do not depend on the
  * shape (the per-vertex sums run in a fixed order).  Host only; EPK_EINVAL
  * for a size out of range.                                                */

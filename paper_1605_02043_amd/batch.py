@@ -1,4 +1,4 @@
-"""Many FLUX5 graphs in one persistent launch, and capacity autotuning."""
+"""Many FLUX5 graphs in one launch per pass, and capacity and launch-shape autotuning."""
 
 from __future__ import annotations
 

@@ -268,6 +268,7 @@ static int batch_build(int32_t n_graphs, epk_plan *const *plans, epk_batch **out
   B->lds_fwd_direct = flux_fwd_lds(B->max_u, B->max_nf, B->max_cap, B->vmajor);
   B->lds_bwd_direct = flux_bwd_lds(B->max_u, B->max_nf, B->max_cap, B->vmajor);
   if (B->lds_fwd_direct > kMaxLdsBytes || B->lds_bwd_direct > kMaxLdsBytes) B->direct_ok = false;
+  B->direct = B->direct_ok;  // the faster kind on the meshes measured, where it can run
   if (B->lds_fwd > kMaxLdsBytes || B->lds_bwd > kMaxLdsBytes) {
     delete B;
     return fail(EPK_ERANGE, "batch needs more LDS than a workgroup may use");

@@ -220,8 +220,10 @@ def test_batch_set_launch_validation():
     with pytest.raises(_lib.EpkError) as e:
         B2.set_launch(64)  # 9 or more edges per lane
     assert e.value.status == _lib.EPK_EINVAL
-    # one workgroup per item: needs one capacity for every graph
-    assert B.info()["direct_ok"] == 1 and B.info()["direct"] == 0
+    # one workgroup per item: needs one capacity for every graph, and is then the default
+    assert B.info()["direct_ok"] == 1 and B.info()["direct"] == 1
+    B.set_launch(0, 0)
+    assert B.info()["direct"] == 0
     B.set_launch(0, 1)
     assert B.info()["direct"] == 1 and B.info()["wg"] == 64
     B.set_launch(256, -1)
