@@ -82,6 +82,42 @@ def test_batch_launch_shapes_bitwise():
             assert torch.equal(B.forward(qd), r0) and torch.equal(B.backward(qd, gd), g0)
 
 
+def _unit_geom(m, rng):
+    nrm = rng.standard_normal((m, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return np.concatenate([nrm, rng.uniform(0.5, 2.0, (m, 1))], axis=1).astype(np.float32)
+
+
+def test_batch_edge_cases_both_launch_kinds():
+    """Empty graphs, a single edge, isolated vertices, a hub and parts with more foreign ids
+    than lanes, in one batch: both launch kinds against the oracle and bitwise equal."""
+    rng = np.random.default_rng(11)
+    graphs = []
+    graphs.append({"edges": np.zeros((0, 2), np.int64), "n": 7})
+    graphs.append({"edges": np.array([[3, 1]]), "n": 6})
+    n, m = 50, 203
+    u = rng.integers(0, n, m)
+    graphs.append({"edges": np.stack([u, (u + 1 + rng.integers(0, n - 1, m)) % n], 1), "n": n + 5})
+    graphs.append({"edges": np.zeros((0, 2), np.int64), "n": 1})
+    graphs.append({"edges": np.stack([np.zeros(299, int), np.arange(1, 300)], 1), "n": 300})
+    n, m = 1200, 5000
+    u = rng.integers(0, n, m)
+    graphs.append({"edges": np.stack([u, (u + 1 + rng.integers(0, n - 1, m)) % n], 1), "n": n})
+    for g in graphs:
+        g["geom"] = _unit_geom(len(g["edges"]), rng)
+    for cap in (16, 512):
+        say(f"case batch edge cases cap {cap}")
+        plans, B = _build(graphs, [cap] * len(graphs))
+        assert B.info()["direct_ok"] == 1
+        outs = []
+        for direct in (1, 0):
+            B.set_launch(0, direct)
+            say(f"  direct {direct}: {B.info()}")
+            qd, gd = _check(graphs, plans, B, f"edge/cap{cap}/direct{direct}")
+            outs.append((B.forward(qd).clone(), B.backward(qd, gd).clone()))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_batch256_and_graph_replay():
     graphs = gen.batch_graphs(256, seed=0)
     caps = [256] * len(graphs)
