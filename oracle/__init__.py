@@ -29,9 +29,11 @@ Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
 CPU tests.  ``cpack.layout`` is also pinned exactly on a hand-derived case
 (``tests/golden/cpack_three_parts.json``), and ``multilevel.partition`` and
-``ggp.partition`` on Figure 1, whose optimum is unique up to part labels.  The exact output of
-``multilevel.partition``, ``ggp.partition``, the two ``baselines`` and, beyond
-that case, ``cpack.layout`` is parity unpinned: it is fixed by their
+``ggp.partition`` on Figure 1, whose optimum is unique up to part labels, and
+on a hand-derived path whose edge ids run out of path order
+(``tests/golden/multilevel_path9.json``).  The exact output of
+``multilevel.partition``, ``ggp.partition``, the two ``baselines`` and
+``cpack.layout`` beyond those cases is parity unpinned: it is fixed by their
 specification and checked only by two independent implementations agreeing bit
 for bit.
 """

@@ -126,6 +126,14 @@ def test_partition_parity_grid64_and_fig1(golden_dir):
     assert part.tolist() == F["ep_parts"] and st_["loads"] == 7
     part, _, st_ = partition(np.array(F["edges"]), F["n"], 3, "input")
     assert st_["loads"] == 9
+    # the hand-derived path case: exact parts and task orders of both growing partitioners
+    H = json.load(open(os.path.join(golden_dir, "multilevel_path9.json")))
+    E = np.array(H["edges"])
+    part, task, st_ = partition(E, H["n"], H["capacity"])
+    assert part.tolist() == H["ep_parts"] and task.tolist() == H["ep_task_order"]
+    assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"] and st_["n_parts"] == H["k"]
+    part, task, _ = partition(E, H["n"], H["capacity"], "ggp")
+    assert part.tolist() == H["ggp_parts"] and task.tolist() == H["ggp_task_order"]
 
 
 def test_partition_parity_tet_mesh():

@@ -345,6 +345,23 @@ def test_multilevel_fig1(golden_dir):
     assert task.tolist() == [0, 1, 3, 2, 4, 5]
 
 
+def test_multilevel_and_ggp_hand_derived_path(golden_dir):
+    """A path whose edge ids are out of path order (tests/golden/multilevel_path9.json): the
+    second part must start from the node most linked to placed nodes, not from the smallest
+    unplaced id, which would swap the last two part labels.  Derived by hand from the growing
+    rules; both partitioners grow the same parts."""
+    import json
+
+    G = json.load(open(os.path.join(golden_dir, "multilevel_path9.json")))
+    E, n, cap = np.array(G["edges"]), G["n"], G["capacity"]
+    part, task, k = multilevel.partition(E, n, cap)
+    assert k == G["k"] and part.tolist() == G["ep_parts"] and task.tolist() == G["ep_task_order"]
+    c = cost.partition_cost(E, n, part, k)
+    assert c["loads"] == G["loads"] and c["cost"] == G["cost"]
+    gp, gt = ggp.partition(E, n, cap)
+    assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
+
+
 @settings(max_examples=60, deadline=None)
 @given(st.integers(2, 40), st.integers(1, 150), st.integers(1, 40), st.integers(0, 10_000))
 def test_multilevel_invariants(n, m, cap, seed):
