@@ -362,6 +362,27 @@ def test_multilevel_and_ggp_hand_derived_path(golden_dir):
     assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
 
 
+def test_multilevel_refinement_hand_derived(golden_dir):
+    """A 5-edge graph where refinement moves one node and lowers the cost from 4 to 3
+    (tests/golden/multilevel_refine5.json, derived by hand): the grown parts, the refined
+    result of the multilevel order and the unrefined result of single-pass growing."""
+    import json
+
+    G = json.load(open(os.path.join(golden_dir, "multilevel_refine5.json")))
+    E, n, cap = np.array(G["edges"]), G["n"], G["capacity"]
+    k, target, _ = multilevel.parameters(len(E), cap)
+    adj, w = multilevel._finest(E, n)
+    grown = multilevel.grow(adj, w, k, target, cap)
+    assert k == G["k"] and grown == G["grown_parts"]
+    assert cost.partition_cost(E, n, np.array(grown), k)["loads"] == G["grown_loads"]
+    part, task, k = multilevel.partition(E, n, cap)
+    assert part.tolist() == G["ep_parts"] and task.tolist() == G["ep_task_order"]
+    c = cost.partition_cost(E, n, part, k)
+    assert c["loads"] == G["loads"] and c["cost"] == G["cost"]
+    gp, gt = ggp.partition(E, n, cap)
+    assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
+
+
 @settings(max_examples=60, deadline=None)
 @given(st.integers(2, 40), st.integers(1, 150), st.integers(1, 40), st.integers(0, 10_000))
 def test_multilevel_invariants(n, m, cap, seed):
