@@ -383,6 +383,25 @@ def test_multilevel_refinement_hand_derived(golden_dir):
     assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
 
 
+def test_coarsen_matching_rules_hand_derived():
+    """One level of heavy-edge matching on small weighted graphs, derived by hand: nodes in
+    ascending id take the unmatched neighbour of largest link weight (not the smallest id),
+    within the coarse-node weight cap, ties to the smaller id; coarse ids follow the visit;
+    node weights and link weights add and links inside a coarse node vanish."""
+    adj = [{1: 1, 2: 3}, {0: 1, 3: 2}, {0: 3, 4: 1}, {1: 2}, {2: 1}]
+    # 0 takes 2 (link 3 beats link 1), 1 takes 3, 4 has no unmatched neighbour left
+    cadj, cw, cmap = multilevel.coarsen(adj, [1] * 5, 2)
+    assert cmap == [0, 1, 0, 1, 2] and cw == [2, 2, 1]
+    assert cadj == [{1: 1, 2: 1}, {0: 1}, {0: 1}]
+    # node 2 weighs 2: 0 + 2 would exceed the cap, so 0 takes 1; 2, 3 and 4 stay single
+    cadj, cw, cmap = multilevel.coarsen(adj, [1, 1, 2, 1, 1], 2)
+    assert cmap == [0, 0, 1, 2, 3] and cw == [2, 2, 1, 1]
+    assert cadj == [{1: 3, 2: 2}, {0: 3, 3: 1}, {0: 2}, {1: 1}]
+    # equal link weights: the smaller id wins
+    cadj, cw, cmap = multilevel.coarsen([{3: 1, 1: 1}, {0: 1}, {}, {0: 1}], [1] * 4, 2)
+    assert cmap == [0, 0, 1, 2] and cw == [2, 1, 1] and cadj == [{2: 1}, {}, {0: 1}]
+
+
 @settings(max_examples=60, deadline=None)
 @given(st.integers(2, 40), st.integers(1, 150), st.integers(1, 40), st.integers(0, 10_000))
 def test_multilevel_invariants(n, m, cap, seed):
