@@ -31,8 +31,9 @@ CPU tests.  ``cpack.layout`` is also pinned exactly on a hand-derived case
 (``tests/golden/cpack_three_parts.json``), and ``multilevel.partition`` and
 ``ggp.partition`` on Figure 1, whose optimum is unique up to part labels, and
 on a hand-derived path whose edge ids run out of path order
-(``tests/golden/multilevel_path9.json``) and a graph where refinement moves a
-node (``tests/golden/multilevel_refine5.json``).  The exact output of
+(``tests/golden/multilevel_path9.json``) and graphs where refinement moves a
+node and where the contiguity pass moves a piece
+(``tests/golden/multilevel_refine5.json``, ``multilevel_contiguity6.json``).  The exact output of
 ``multilevel.partition``, ``ggp.partition``, the two ``baselines`` and
 ``cpack.layout`` beyond those cases is parity unpinned: it is fixed by their
 specification and checked only by two independent implementations agreeing bit

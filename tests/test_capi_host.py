@@ -134,13 +134,14 @@ def test_partition_parity_grid64_and_fig1(golden_dir):
     assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"] and st_["n_parts"] == H["k"]
     part, task, _ = partition(E, H["n"], H["capacity"], "ggp")
     assert part.tolist() == H["ggp_parts"] and task.tolist() == H["ggp_task_order"]
-    H = json.load(open(os.path.join(golden_dir, "multilevel_refine5.json")))  # refinement moves one node
-    E = np.array(H["edges"])
-    part, task, st_ = partition(E, H["n"], H["capacity"])
-    assert part.tolist() == H["ep_parts"] and task.tolist() == H["ep_task_order"]
-    assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"]
-    part, task, _ = partition(E, H["n"], H["capacity"], "ggp")
-    assert part.tolist() == H["ggp_parts"] and task.tolist() == H["ggp_task_order"]
+    for name in ("multilevel_refine5.json", "multilevel_contiguity6.json"):  # refinement; contiguity
+        H = json.load(open(os.path.join(golden_dir, name)))
+        E = np.array(H["edges"])
+        part, task, st_ = partition(E, H["n"], H["capacity"])
+        assert part.tolist() == H["ep_parts"] and task.tolist() == H["ep_task_order"]
+        assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"]
+        part, task, _ = partition(E, H["n"], H["capacity"], "ggp")
+        assert part.tolist() == H["ggp_parts"] and task.tolist() == H["ggp_task_order"]
 
 
 def test_partition_parity_tet_mesh():

@@ -383,6 +383,30 @@ def test_multilevel_refinement_hand_derived(golden_dir):
     assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
 
 
+def test_multilevel_contiguity_hand_derived(golden_dir):
+    """A 6-edge multigraph where refinement splits a part in two pieces and the contiguity pass
+    moves the lighter-id piece away, lowering the cost from 2 to 1
+    (tests/golden/multilevel_contiguity6.json, derived by hand), step by step."""
+    import json
+
+    G = json.load(open(os.path.join(golden_dir, "multilevel_contiguity6.json")))
+    E, n, cap = np.array(G["edges"]), G["n"], G["capacity"]
+    k, target, _ = multilevel.parameters(len(E), cap)
+    adj, w = multilevel._finest(E, n)
+    p = multilevel.grow(adj, w, k, target, cap)
+    assert p == G["grown_parts"]
+    p = multilevel.refine(adj, w, p, k, cap)
+    assert p == G["refined_parts"]
+    p = multilevel.contiguity(adj, w, p, k, cap)
+    assert p == G["ep_parts"]
+    part, task, k = multilevel.partition(E, n, cap)
+    assert part.tolist() == G["ep_parts"] and task.tolist() == G["ep_task_order"]
+    c = cost.partition_cost(E, n, part, k)
+    assert c["loads"] == G["loads"] and c["cost"] == G["cost"]
+    gp, gt = ggp.partition(E, n, cap)
+    assert gp.tolist() == G["ggp_parts"] and gt.tolist() == G["ggp_task_order"]
+
+
 def test_coarsen_matching_rules_hand_derived():
     """One level of heavy-edge matching on small weighted graphs, derived by hand: nodes in
     ascending id take the unmatched neighbour of largest link weight (not the smallest id),
