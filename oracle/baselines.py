@@ -18,9 +18,11 @@ edges, "least loaded" = fewest edges, then smaller id:
   otherwise, or no candidate   -> least loaded candidate overall.
 Tasks inside a part run in ascending edge id.
 
-Parity unpinned beyond the pins in the tests (capacity, balance, closed forms):
-the exact placement is fixed by this specification and checked against the
-library bit for bit.
+Greedy is pinned exactly on a hand-derived 9-edge case
+(tests/golden/greedy_vertex_cut9.json).  Parity unpinned beyond that and the
+other pins in the tests (capacity, balance, closed forms, the published
+SplitMix64 outputs): the exact placement is fixed by this specification and
+checked against the library bit for bit.
 """
 
 from __future__ import annotations

@@ -518,6 +518,23 @@ def test_random_baseline_is_balanced_permutation(m, cap):
     assert (part[task] == np.arange(m) // cap).all()
 
 
+def test_greedy_baseline_hand_derived(golden_dir):
+    """Greedy vertex-cut placement on a 9-edge graph, derived by hand
+    (tests/golden/greedy_vertex_cut9.json): shared part, the endpoint with more unplaced
+    edges, one placed endpoint, and the fall-back to the least loaded part when the preferred
+    parts are full."""
+    import json
+
+    from oracle.baselines import greedy_partition
+
+    G = json.load(open(os.path.join(golden_dir, "greedy_vertex_cut9.json")))
+    E = np.array(G["edges"])
+    part, task = greedy_partition(E, G["n"], G["capacity"])
+    assert part.tolist() == G["greedy_parts"] and task.tolist() == G["greedy_task_order"]
+    c = cost.partition_cost(E, G["n"], part, G["k"])
+    assert c["loads"] == G["loads"] and c["cost"] == G["cost"]
+
+
 def test_greedy_baseline_capacity_and_closed_forms():
     from oracle.baselines import greedy_partition
 
