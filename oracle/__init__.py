@@ -27,17 +27,18 @@ GPU Caching Problems"):
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
-CPU tests.  ``cpack.layout`` is also pinned exactly on a hand-derived case
-(``tests/golden/cpack_three_parts.json``), and ``multilevel.partition`` and
-``ggp.partition`` on Figure 1, whose optimum is unique up to part labels, and
-on a hand-derived path whose edge ids run out of path order
-(``tests/golden/multilevel_path9.json``) and graphs where refinement moves a
-node and where the contiguity pass moves a piece
-(``tests/golden/multilevel_refine5.json``, ``multilevel_contiguity6.json``).  The exact output of
-``multilevel.partition``, ``ggp.partition``, the two ``baselines`` and
-``cpack.layout`` beyond those cases is parity unpinned: it is fixed by their
-specification and checked only by two independent implementations agreeing bit
-for bit.
+CPU tests.  The partitioners and the layout are pinned exactly on hand-derived
+cases under tests/golden/: ``cpack.layout`` on three parts
+(``cpack_three_parts.json``); ``multilevel.partition`` and ``ggp.partition`` on
+Figure 1 (``fig1.json``, whose optimum is unique up to part labels), on a path
+whose edge ids run out of path order (``multilevel_path9.json``) and on graphs
+where refinement moves a node and where the contiguity pass moves a piece
+(``multilevel_refine5.json``, ``multilevel_contiguity6.json``), with one
+coarsening level pinned on small weighted graphs in the tests;
+``baselines.greedy_partition`` on a 9-edge case (``greedy_vertex_cut9.json``).
+Beyond those cases, the exact output of the partitioners, the baselines and
+the layout is parity unpinned: it is fixed by their specification and checked
+only by two independent implementations agreeing bit for bit.
 """
 
 from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines  # noqa: F401
