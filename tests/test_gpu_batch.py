@@ -118,6 +118,31 @@ def test_batch_edge_cases_both_launch_kinds():
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
+def test_batch_hubs_vertex_major_both_launch_kinds():
+    """Hub-heavy graphs put the batch in the vertex-major workspace (slots scattered through
+    per-entry slot indices), and at capacity 4 the largest hub has more partials than one
+    reduction thread takes: both launch kinds against the oracle and bitwise equal."""
+    rng = np.random.default_rng(13)
+    graphs = []
+    for leaves in (299, 150, 400):
+        graphs.append({"edges": np.stack([np.zeros(leaves, int), np.arange(1, leaves + 1)], 1), "n": leaves + 1})
+    n, m = 40, 120
+    u = rng.integers(0, n, m)
+    graphs.append({"edges": np.stack([u, (u + 1 + rng.integers(0, n - 1, m)) % n], 1), "n": n})
+    for g in graphs:
+        g["geom"] = _unit_geom(len(g["edges"]), rng)
+    for cap in (4, 16):
+        say(f"case batch hubs cap {cap}")
+        plans, B = _build(graphs, [cap] * len(graphs))
+        outs = []
+        for direct in (1, 0):
+            B.set_launch(0, direct)
+            say(f"  direct {direct}: {B.info()}")
+            qd, gd = _check(graphs, plans, B, f"hubs/cap{cap}/direct{direct}")
+            outs.append((B.forward(qd).clone(), B.backward(qd, gd).clone()))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_batch256_and_graph_replay():
     graphs = gen.batch_graphs(256, seed=0)
     caps = [256] * len(graphs)
