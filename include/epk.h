@@ -121,6 +121,16 @@ int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *
 /* Plan = partition + data packing along the task order (Section 4.1) + the
  * device image the kernels read.  Host only, synchronous.                */
 int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind, epk_plan **out);
+/* The same plan from a partition the caller made (Definition 2's output,
+ * e.g. from an offline partitioner): part_of_edge[m] in [0, n_parts);
+ * task_order[m] lists the edges part by part, parts ascending (NULL:
+ * ascending edge id inside a part).  Both host, caller-owned, read during
+ * the call.  EPK_EINVAL for an entry outside [0, n_parts) or a task order
+ * that is not such a permutation; EPK_ERANGE if a part holds more than
+ * `capacity` edges (a part's records fill one block of `capacity` slots).
+ * Host only, synchronous.                                                 */
+int epk_plan_create_partitioned(const epk_graph *g, int32_t capacity, int64_t n_parts, const int32_t *part_of_edge,
+                                const int32_t *task_order, int32_t kind, epk_plan **out);
 /* Bytes of the device image and of the per-call workspace (replicated-vertex
  * partials).  Both are caller-allocated; alignment 256 bytes.             */
 int epk_plan_device_bytes(const epk_plan *p, size_t *image_bytes, size_t *workspace_bytes);

@@ -16,14 +16,19 @@ balance factor max / mean stays <= c / (c - floor(c/20)) (1.05 at c = 256).
 
 1. Coarsen while the graph has more than 16k nodes: visit nodes in ascending
    id; an unmatched node u joins the unmatched neighbour v != u of largest link
-   weight (ties: smallest id) with w(u) + w(v) <= W = max(2, floor(c/32)); else
-   it stays single.  Coarse ids follow the visiting order; weights and link
-   weights add; links inside a coarse node vanish.  A level that keeps more
+   weight (ties: smallest id) with w(u) + w(v) <= W; else it stays single.
+   W = min(max(2, floor(c/32)), floor(c/20) + 1): a coarse node weighs at most
+   one more than the room the capacity leaves above the growth target, so a
+   part below the target always has room for the next node and growing fills
+   every part to the target (with no room, c < 20, W = 1 and nothing merges).
+   Coarse ids follow the visiting order; weights and link weights add; links
+   inside a coarse node vanish.  A level that keeps more
    than 90% of the nodes is discarded and coarsening stops.
 2. Partition the coarsest graph by greedy growing (parts 0..k-1 in turn, as in
    ``ggp`` but with node weights: a candidate must fit under c; candidates that
-   do not fit are dropped from the queues), place the remainder, then refine,
-   make parts contiguous, refine.
+   do not fit are dropped from the queues), place any remainder on a part with
+   room (by the weight rule above there is none), then refine, make parts
+   contiguous, refine.
 3. Project level by level to the finest graph; refine; make parts contiguous.
 
 Inside a part, tasks run in ascending edge id.
@@ -39,12 +44,22 @@ import numpy as np
 from .graph import contracted_links, incidence
 
 
+def max_node_weight(cap: int) -> int:
+    """Largest coarse-node weight: at most the room (floor(cap/20)) plus one.
+
+    Growth fills part p while its size is below the target T <= cap - floor(cap/20);
+    a node of weight w <= floor(cap/20) + 1 then always fits (size + w <= T - 1 + w
+    <= cap), so every part reaches T and k*T >= m places every node.
+    """
+    return min(max(2, cap // 32), cap // 20 + 1)
+
+
 def parameters(m: int, cap: int):
     """(k, growth target, maximum coarse-node weight)."""
     if m == 0:
-        return 0, 0, max(2, cap // 32)
+        return 0, 0, max_node_weight(cap)
     k = math.ceil(m / (cap - cap // 20))
-    return k, math.ceil(m / k), max(2, cap // 32)
+    return k, math.ceil(m / k), max_node_weight(cap)
 
 
 def _finest(edges, n):
@@ -144,7 +159,10 @@ def grow(adj, w, k, target, cap):
             if conn:
                 p = max(conn, key=lambda q: (conn[q], -q))
             else:
-                p = min(range(k), key=lambda q: (sizes[q], q))
+                room = [q for q in range(k) if sizes[q] + w[u] <= cap]
+                if not room:
+                    raise RuntimeError("no part has room for a remaining node")
+                p = min(room, key=lambda q: (sizes[q], q))
             part[u] = p
             sizes[p] += w[u]
     return part

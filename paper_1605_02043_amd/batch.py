@@ -7,7 +7,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import Graph, check, i32p, i64p, lib
-from .plan import Plan, _dptr, _full_device, _stream_handle, make_graph
+from .plan import Plan, _dptr, _full_device, _stream_handle, check_tensor, make_graph
 
 
 class Batch:
@@ -63,17 +63,31 @@ class Batch:
         check(lib.epk_batch_upload(self._h, _dptr(self.image), _stream_handle(torch, dev)))
         return self
 
+    def _check_state(self, t, name):
+        if self.device is None:
+            raise ValueError("batch is not uploaded")
+        check_tensor(t, self.device, self.n, 5, name)
+
     def forward(self, q, out=None):
+        """r for the concatenated packed states q[sum n][5] of all graphs."""
         import torch
 
+        self._check_state(q, "q")
+        if out is not None:
+            self._check_state(out, "out")
         r = out if out is not None else torch.empty_like(q)
         check(lib.epk_batch_forward(self._h, _dptr(q), _dptr(r), _dptr(self.workspace),
                                     _stream_handle(torch, self.device)))
         return r
 
     def backward(self, q, g_r, out=None):
+        """g_q = (dr/dq)^T g_r for the concatenated packed q, g_r [sum n][5]."""
         import torch
 
+        self._check_state(q, "q")
+        self._check_state(g_r, "g_r")
+        if out is not None:
+            self._check_state(out, "out")
         g_q = out if out is not None else torch.empty_like(q)
         check(lib.epk_batch_backward(self._h, _dptr(q), _dptr(g_r), _dptr(g_q), _dptr(self.workspace),
                                      _stream_handle(torch, self.device)))

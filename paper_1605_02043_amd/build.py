@@ -26,7 +26,7 @@ HIP_SOURCES = ["kernels.hip", "api.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-munsafe-fp-atomics", "-Wno-unused-command-line-argument"]
+             "-Wno-unused-command-line-argument"]
 
 
 def _run(cmd):

@@ -46,13 +46,21 @@ uint64_t splitmix64(uint64_t x);
 void random_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
 void greedy_vertex_cut(int32_t n, int64_t m, const int32_t *uv, int32_t cap, std::vector<int32_t> &part,
                        std::vector<int32_t> &task);
+// Thrown when a partitioner cannot place a node without passing the capacity.
+struct CapacityExceeded {};
 int64_t multilevel_parts(int64_t m, int32_t cap);
+int32_t multilevel_max_node_weight(int32_t cap);
 void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
                 std::vector<int32_t> &task);
 void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const std::vector<int32_t> &part,
                      const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st);
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out);
+// A caller's partition: part_in[m] in [0, k); task_in[m] (may be NULL: parts
+// ascending, edge id inside a part) a permutation listing parts in order.
+// Capacity is not checked here (plan_build refuses parts above it).
+int given_partition(const epk_graph *g, int64_t k, const int32_t *part_in, const int32_t *task_in,
+                    std::vector<int32_t> &part, std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out);
 
 // ------------------------------------------------------------ device image
 
@@ -169,7 +177,10 @@ void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its curr
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);
-epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status);
+// order < 0: the partition comes from the caller (given_k parts, given_part,
+// given_task as for given_partition).
+epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status,
+                     int64_t given_k = 0, const int32_t *given_part = nullptr, const int32_t *given_task = nullptr);
 // Reduction records, one per replicated vertex: its packed id and its (at
 // most kRecSlots) slots, -1 past the last; a first slot of -1 sends the
 // vertex to the slot lists (more slots than a record holds).

@@ -5,10 +5,15 @@
 // count the auxiliary edges of D' between two nodes.  Capacity: at most c
 // edges per part, k = ceil(m / (c - c/20)) parts, growth target ceil(m / k).
 //  1. coarsen by heavy-edge matching (ascending visit, heaviest unmatched
-//     neighbour, ties smallest id, combined weight <= max(2, c/32)) while the
-//     graph has more than 16k nodes and a level removes at least 10% of them;
-//  2. greedy growing on the coarsest graph, placement of the remainder,
-//     refine, contiguity, refine;
+//     neighbour, ties smallest id, combined weight <= W) while the graph has
+//     more than 16k nodes and a level removes at least 10% of them.
+//     W = min(max(2, c/32), c/20 + 1): a coarse node weighs at most one more
+//     than the room above the growth target T <= c - c/20, so a part below T
+//     always fits the next node, every part grows to T and k*T >= m places
+//     every node (c < 20 leaves no room: W = 1, nothing merges);
+//  2. greedy growing on the coarsest graph, placement of any remainder on a
+//     part with room (none is left by the rule above), refine, contiguity,
+//     refine;
 //  3. project to each finer level, refine, contiguity.
 // refine: up to 8 passes; each node (ascending id) moves to the linked part
 // with the largest positive gain (link weight to it minus to its own part;
@@ -196,9 +201,9 @@ std::vector<int32_t> grow(const LGraph &G, int32_t k, int64_t target, int32_t ca
     }
     for (int32_t q : cl) conn[q] = 0;
     if (best < 0) {
-      best = 0;
-      for (int32_t q = 1; q < k; ++q)
-        if (sizes[q] < sizes[best]) best = q;
+      for (int32_t q = 0; q < k; ++q)
+        if (sizes[q] + G.w[u] <= cap && (best < 0 || sizes[q] < sizes[best])) best = q;
+      if (best < 0) throw CapacityExceeded{};
     }
     part[u] = best;
     sizes[best] += G.w[u];
@@ -332,6 +337,8 @@ void contiguity(const LGraph &G, std::vector<int32_t> &part, int32_t k, int32_t 
 
 }  // namespace
 
+int32_t multilevel_max_node_weight(int32_t cap) { return std::min(std::max(2, cap / 32), cap / 20 + 1); }
+
 int64_t multilevel_parts(int64_t m, int32_t cap) {
   if (m == 0) return 0;
   const int64_t t0 = cap - cap / 20;
@@ -345,7 +352,7 @@ void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::ve
   if (m == 0) return;
   const int32_t k = int32_t(multilevel_parts(m, cap));
   const int64_t target = (m + k - 1) / k;
-  const int32_t maxw = std::max(2, cap / 32);
+  const int32_t maxw = multilevel_max_node_weight(cap);
   std::vector<LGraph> levels;
   std::vector<std::vector<int32_t>> cmaps;
   levels.push_back(finest(m, nbr));

@@ -241,11 +241,55 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
     const auto t1 = std::chrono::steady_clock::now();
     partition_stats(g->n_vertices, m, g->edge_uv, k, part, task, inc, st);
     st.partition_seconds = std::chrono::duration<double>(t1 - t0).count();
+    // every part holds at most cap edges (Eq. 1's balance as a hard capacity)
+    if (st.max_part_edges > cap) return fail(EPK_ERANGE, "a part holds more edges than the capacity");
     if (inc_out) *inc_out = std::move(inc);
   } catch (const std::bad_alloc &) {
     return fail(EPK_ENOMEM, "host allocation failed while partitioning");
   } catch (const Cancelled &) {
     return fail(EPK_ECANCELED, "partition cancelled");
+  } catch (const CapacityExceeded &) {
+    return fail(EPK_ERANGE, "a part would hold more edges than the capacity");
+  }
+  return EPK_OK;
+}
+
+int given_partition(const epk_graph *g, int64_t k, const int32_t *part_in, const int32_t *task_in,
+                    std::vector<int32_t> &part, std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
+  const int64_t m = g->n_edges;
+  if (m > 0 && !part_in) return fail(EPK_EINVAL, "part_of_edge is NULL");
+  if (k < 0 || (m > 0 && k < 1) || k > (int64_t(1) << 31) - 1) return fail(EPK_EINVAL, "n_parts out of range");
+  std::memset(&st, 0, sizeof(st));
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    part.assign(part_in, part_in + m);
+    for (int64_t e = 0; e < m; ++e)
+      if (part[e] < 0 || part[e] >= k) return fail(EPK_EINVAL, "part_of_edge entry outside [0, n_parts)");
+    task.resize(size_t(m));
+    if (task_in) {
+      // a permutation of the edges listing the parts in ascending order
+      std::vector<char> seen(size_t(m), 0);
+      for (int64_t j = 0; j < m; ++j) {
+        const int32_t e = task_in[j];
+        if (e < 0 || e >= m || seen[e]) return fail(EPK_EINVAL, "task_order is not a permutation of the edges");
+        seen[e] = 1;
+        if (j > 0 && part[e] < part[task_in[j - 1]]) return fail(EPK_EINVAL, "task_order does not list parts in ascending order");
+        task[j] = e;
+      }
+    } else {  // parts ascending, edge id inside a part
+      std::vector<int64_t> off(size_t(k) + 1, 0);
+      for (int64_t e = 0; e < m; ++e) off[part[e] + 1]++;
+      for (int64_t q = 0; q < k; ++q) off[q + 1] += off[q];
+      for (int64_t e = 0; e < m; ++e) task[off[part[e]]++] = int32_t(e);
+    }
+    Incidence inc;
+    build_incidence(g->n_vertices, m, g->edge_uv, inc);
+    const auto t1 = std::chrono::steady_clock::now();
+    partition_stats(g->n_vertices, m, g->edge_uv, k, part, task, inc, st);
+    st.partition_seconds = std::chrono::duration<double>(t1 - t0).count();
+    if (inc_out) *inc_out = std::move(inc);
+  } catch (const std::bad_alloc &) {
+    return fail(EPK_ENOMEM, "host allocation failed while reading the partition");
   }
   return EPK_OK;
 }

@@ -134,7 +134,8 @@ struct Build {
 
 }  // namespace
 
-epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status) {
+epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status, int64_t given_k,
+                     const int32_t *given_part, const int32_t *given_task) {
   *status = EPK_OK;
   if (kind != EPK_FLUX5 && kind != EPK_SPMV) {
     *status = fail(EPK_EINVAL, "unknown kind");
@@ -166,7 +167,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->m = g->n_edges;
     P->wg = kind == EPK_SPMV ? std::max(64, ((cap + 63) / 64) * 64) : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
     Incidence inc;
-    int s = run_partition(g, cap, order, P->part, P->task, P->stats, &inc);
+    int s = order >= 0 ? run_partition(g, cap, order, P->part, P->task, P->stats, &inc)
+                       : given_partition(g, given_k, given_part, given_task, P->part, P->task, P->stats, &inc);
     if (s) {
       delete P;
       *status = s;
@@ -183,6 +185,14 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::vector<int64_t> poff(size_t(k) + 1, 0);
     for (int64_t e = 0; e < m; ++e) poff[P->part[e] + 1]++;
     for (int64_t q = 0; q < k; ++q) poff[q + 1] += poff[q];
+    // A part's records fill a block of cap slots (part p's at p * cap): a part
+    // above the capacity would overwrite its neighbour's block.
+    for (int64_t q = 0; q < k; ++q)
+      if (poff[q + 1] - poff[q] > cap) {
+        delete P;
+        *status = fail(EPK_ERANGE, "a part holds more edges than the capacity");
+        return nullptr;
+      }
     auto cls = [&](int32_t w) { return (kind == EPK_SPMV && w >= P->n_x) ? 1 : 0; };
 
     // ---- first-touch packing, per part ordered by the next part that touches
@@ -585,6 +595,18 @@ int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t
   *out = nullptr;
   int s = EPK_OK;
   epk_plan *p = epk::plan_build(g, capacity, order, kind, &s);
+  if (!p) return s ? s : epk::fail(EPK_EINVAL, "plan build failed");
+  *out = p;
+  return EPK_OK;
+}
+
+int epk_plan_create_partitioned(const epk_graph *g, int32_t capacity, int64_t n_parts, const int32_t *part_of_edge,
+                                const int32_t *task_order, int32_t kind, epk_plan **out) {
+  epk::clear_error();
+  if (!out) return epk::fail(EPK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int s = EPK_OK;
+  epk_plan *p = epk::plan_build(g, capacity, -1, kind, &s, n_parts, part_of_edge, task_order);
   if (!p) return s ? s : epk::fail(EPK_EINVAL, "plan build failed");
   *out = p;
   return EPK_OK;

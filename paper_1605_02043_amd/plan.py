@@ -43,6 +43,22 @@ def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep"):
     return part, task, st.as_dict()
 
 
+def check_tensor(t, device, rows, cols, name):
+    """A device buffer handed to the kernels: a contiguous float32 tensor on `device` of
+    shape (rows, cols), or of rows elements when cols == 1."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch.Tensor")
+    if t.device != device or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on {device}")
+    if cols == 1:
+        if t.numel() != rows:
+            raise ValueError(f"{name} must have {rows} elements")
+    elif tuple(t.shape) != (rows, cols):
+        raise ValueError(f"{name} must have shape ({rows}, {cols})")
+
+
 def _full_device(torch, device):
     """torch.device with an explicit index ('cuda' -> 'cuda:<current>')."""
     dev = torch.device(device)
@@ -81,6 +97,32 @@ class Plan:
         self.image = None
         self.workspace = None
         self.device = None
+
+    @classmethod
+    def from_partition(cls, edges, n: int, cap: int, geom, part, task=None, n_parts: int | None = None,
+                       kind: str = "flux5", n_x: int = 0):
+        """Plan from a caller's edge partition (part[m] in [0, n_parts); task: the edges part by
+        part, parts ascending, or None for ascending edge id inside a part).  A part holding more
+        than cap edges is refused (EpkError, status EPK_ERANGE)."""
+        self = cls.__new__(cls)
+        self.kind, self.n, self.n_x, self.m, self.cap = kind, int(n), int(n_x), int(len(edges)), int(cap)
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        if part.shape != (self.m,):
+            raise ValueError(f"part must have {self.m} entries")
+        if task is not None:
+            task = np.ascontiguousarray(task, dtype=np.int32)
+            if task.shape != (self.m,):
+                raise ValueError(f"task must have {self.m} entries")
+        k = int(n_parts) if n_parts is not None else (int(part.max()) + 1 if self.m else 0)
+        gs, keep = make_graph(edges, n, geom, n_x)
+        h = C.c_void_p()
+        self._h = None
+        check(lib.epk_plan_create_partitioned(C.byref(gs), int(cap), k, i32p(part), i32p(task), _lib.KIND[kind],
+                                              C.byref(h)))
+        del keep
+        self._h = h
+        self.image = self.workspace = self.device = None
+        return self
 
     @classmethod
     def _adopt(cls, handle, n: int, m: int, cap: int, kind: str = "flux5", n_x: int = 0):
@@ -170,21 +212,17 @@ class Plan:
         return self
 
     def _check_state(self, t, rows, cols, name):
-        import torch
-
-        if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device}")
-        if cols == 1:
-            if t.numel() != rows:
-                raise ValueError(f"{name} must have {rows} elements")
-        elif tuple(t.shape) != (rows, cols):
-            raise ValueError(f"{name} must have shape ({rows}, {cols})")
+        if self.device is None:
+            raise ValueError("plan is not uploaded")
+        check_tensor(t, self.device, rows, cols, name)
 
     def forward(self, q, dt: float | None = None, out=None):
         """r (and q_new = q + dt r if dt is given) for packed states q[n][5]."""
         import torch
 
         self._check_state(q, self.n, 5, "q")
+        if out is not None:
+            self._check_state(out, self.n, 5, "out")
         r = out if out is not None else torch.empty_like(q)
         qn = torch.empty_like(q) if dt is not None else None
         check(lib.epk_forward(self._h, _dptr(q), _dptr(r), float(dt or 0.0), _dptr(qn), _dptr(self.workspace),
@@ -197,6 +235,8 @@ class Plan:
 
         self._check_state(q, self.n, 5, "q")
         self._check_state(g_r, self.n, 5, "g_r")
+        if out is not None:
+            self._check_state(out, self.n, 5, "out")
         g_q = out if out is not None else torch.empty_like(q)
         check(lib.epk_backward(self._h, _dptr(q), _dptr(g_r), _dptr(g_q), _dptr(self.workspace),
                                _stream_handle(torch, self.device)))
@@ -207,6 +247,8 @@ class Plan:
         import torch
 
         self._check_state(x, self.n_x, 1, "x")
+        if out is not None:
+            self._check_state(out, self.n - self.n_x, 1, "out")
         y = out if out is not None else torch.empty(self.n - self.n_x, dtype=torch.float32, device=self.device)
         check(lib.epk_spmv(self._h, _dptr(x), _dptr(y), _dptr(self.workspace), _stream_handle(torch, self.device)))
         return y

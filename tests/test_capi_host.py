@@ -115,6 +115,22 @@ def test_partition_parity_random(n, m, cap, seed, order):
     _check_parity(E, n, cap, order)
 
 
+def test_partition_capacity_sweep_bit_equal():
+    """Capacities 1-64 on small random multigraphs: the multilevel partition of the library
+    equals the oracle's bit for bit and no part holds more than the capacity (Eq. 1 read as
+    a hard capacity).  Sizes reach the coarsening regime (m > 16k) for every capacity from
+    17 up, where weight-2 coarse nodes once overflowed parts at capacities 17-19."""
+    rng = np.random.default_rng(20240)
+    for cap in range(1, 65):
+        for n, lo, hi in ((2, 16, 24), (7, 16, 24), (40, 16, 24), (40, 1, 16)):
+            m = int(rng.integers(lo * cap, hi * cap))  # 16k < m from lo = 16 on
+            u = rng.integers(0, n, m)
+            v = (u + 1 + rng.integers(0, n - 1, m)) % n
+            E = np.stack([u, v], 1).astype(np.int32)
+            part, _, _, _ = _check_parity(E, n, cap, "ep")
+            assert np.bincount(part).max() <= cap, (cap, n, m)
+
+
 def test_partition_parity_grid64_and_fig1(golden_dir):
     G = gen.grid2d(64, 64, seed=0)
     for order in ("ep", "ggp", "input", "random", "greedy"):
@@ -294,3 +310,94 @@ def test_slot_layout_choice_and_bytes():
     g = spmv_graph(R, R["shuffle"])
     S = Plan(g["edges"], g["n"], 256, g["w"], kind="spmv", n_x=g["n_x"])
     assert S.info()["vertex_major"] == 1
+
+
+def test_plan_from_caller_partition():
+    """A plan built from a caller's partition equals the library's own plan for the same
+    partition (layout and stats), and a part holding more edges than the capacity is refused
+    before anything is packed (each part's records fill one block of cap slots)."""
+    T = gen.tet_mesh(6, 6, 6, seed=3)
+    E, n, geom = T["edges"], T["n"], T["geom"].astype(np.float32)
+    P = Plan(E, n, 64, geom)
+    part, task = P.part_of_edge()
+    Q = Plan.from_partition(E, n, 64, geom, part, task, n_parts=P.stats["n_parts"])
+    for key in ("n_parts", "loads", "cost", "replicated", "slots", "aux_cut", "max_part_edges"):
+        assert Q.stats[key] == P.stats[key], key
+    a, b = P.layout(), Q.layout()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(P.perm(), Q.perm())
+    assert P.info() == Q.info()
+    # default task order: ascending edge id inside a part (the EP order's own rule)
+    R = Plan.from_partition(E, n, 64, geom, part)
+    assert np.array_equal(R.part_of_edge()[1], task)
+    # a part above the capacity: 65 edges in part 0
+    over = part.copy()
+    moved = np.flatnonzero(part == 1)[: 65 - int((part == 0).sum())]
+    over[moved] = 0
+    assert (over == 0).sum() == 65
+    with pytest.raises(_lib.EpkError) as e:
+        Plan.from_partition(E, n, 64, geom, over, n_parts=P.stats["n_parts"])
+    assert e.value.status == _lib.EPK_ERANGE
+    # the same partition fits a capacity of 65
+    Plan.from_partition(E, n, 65, geom, over, n_parts=P.stats["n_parts"])
+    with pytest.raises(_lib.EpkError) as e:  # an entry outside [0, n_parts)
+        Plan.from_partition(E, n, 64, geom, part, n_parts=int(part.max()))
+    assert e.value.status == _lib.EPK_EINVAL
+    bad = task.copy()
+    bad[[0, -1]] = bad[[-1, 0]]  # parts out of order
+    with pytest.raises(_lib.EpkError) as e:
+        Plan.from_partition(E, n, 64, geom, part, bad)
+    assert e.value.status == _lib.EPK_EINVAL
+    bad = task.copy()
+    bad[1] = bad[0]  # not a permutation
+    with pytest.raises(_lib.EpkError) as e:
+        Plan.from_partition(E, n, 64, geom, part, bad)
+    assert e.value.status == _lib.EPK_EINVAL
+
+
+def test_binding_checks_device_buffers():
+    """The binding refuses buffers the kernels would read or write out of bounds (wrong
+    dtype, shape, row count, layout or device) before any library call, for Plan and Batch
+    inputs and outputs alike.  Run on CPU tensors with the device set by hand: nothing
+    here reaches the library's device entry points."""
+    import torch
+
+    from paper_1605_02043_amd.batch import Batch
+
+    T = gen.tet_mesh(4, 4, 4, seed=0)
+    P = Plan(T["edges"], T["n"], 64, T["geom"].astype(np.float32))
+    n = T["n"]
+    good = torch.zeros(n, 5)
+    with pytest.raises(ValueError, match="not uploaded"):
+        P.forward(good)
+    P.device = torch.device("cpu")
+    bad = [torch.zeros(n, 5, dtype=torch.float64), torch.zeros(n - 1, 5), torch.zeros(n, 4),
+           torch.zeros(5, n).t(), torch.zeros(n * 5), np.zeros((n, 5), np.float32)]
+    for b in bad:
+        with pytest.raises(ValueError):
+            P.forward(b)
+        with pytest.raises(ValueError):
+            P.forward(good, out=b)
+        with pytest.raises(ValueError):
+            P.backward(good, b)
+        with pytest.raises(ValueError):
+            P.backward(good, good, out=b)
+    graphs = gen.batch_graphs(3, seed=1, lo=200, hi=600)
+    B = Batch([Plan(g["edges"], g["n"], 128, g["geom"].astype(np.float32)) for g in graphs])
+    good = torch.zeros(B.n, 5)
+    with pytest.raises(ValueError, match="not uploaded"):
+        B.forward(good)
+    B.device = torch.device("cpu")
+    for b in (torch.zeros(B.n - 1, 5), torch.zeros(B.n, 5, dtype=torch.float16), torch.zeros(5, B.n).t(),
+              torch.zeros(graphs[0]["n"], 5)):
+        with pytest.raises(ValueError):
+            B.forward(b)
+        with pytest.raises(ValueError):
+            B.forward(good, out=b)
+        with pytest.raises(ValueError):
+            B.backward(good, b)
+        with pytest.raises(ValueError):
+            B.backward(b, good)
+        with pytest.raises(ValueError):
+            B.backward(good, good, out=b)

@@ -447,6 +447,29 @@ def test_multilevel_invariants(n, m, cap, seed):
     assert c["loads"] == c["cost"] + c["n_active"]
 
 
+def test_multilevel_capacity_regression_no_room():
+    """Below cap 20 the capacity leaves no room above the growth target (k = ceil(m/cap)).
+    Coarse nodes of weight 2 then stalled growth one short of the target and the rest
+    overflowed a part (this graph gave a part of 18 edges at cap 17).  The node-weight
+    bound (room + 1, so 1 here) keeps every part within the capacity (Eq. 1, Section 3.2)."""
+    E = _random_graph(np.random.default_rng(0), 2, 146)
+    assert multilevel.max_node_weight(17) == 1
+    part, task, k = multilevel.partition(E, 2, 17)
+    assert k == 9 and np.bincount(part, minlength=k).max() <= 17
+    assert sorted(task.tolist()) == list(range(146))
+
+
+@pytest.mark.parametrize("cap", [1, 5, 16, 17, 18, 19, 20, 21, 39, 40, 63, 64, 127, 256, 512, 1024])
+def test_multilevel_node_weight_within_room(cap):
+    """The coarse-node weight bound never exceeds the room above the target plus one,
+    so a part below the target always fits the next node; from cap 20 up it is the
+    plain max(2, cap/32) rule."""
+    w = multilevel.max_node_weight(cap)
+    assert 1 <= w <= cap // 20 + 1
+    if cap >= 20:
+        assert w == max(2, cap // 32)
+
+
 @pytest.mark.parametrize("seed", range(10))
 def test_multilevel_not_below_brute_force(seed):
     rng = np.random.default_rng(100 + seed)
