@@ -27,18 +27,23 @@ GPU Caching Problems"):
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
-CPU tests.  The partitioners and the layout are pinned exactly on hand-derived
-cases under tests/golden/: ``cpack.layout`` on three parts
-(``cpack_three_parts.json``); ``multilevel.partition`` and ``ggp.partition`` on
-Figure 1 (``fig1.json``, whose optimum is unique up to part labels), on a path
+CPU tests; the tolerance floors (``flux.forward_abs``, ``flux.backward_abs``)
+and the signed forward are pinned on one hand-derived edge.  ``cpack.layout``
+is plain first-touch packing and pinned by that definition recomputed in the
+tests and on a hand-derived three-part case (``cpack_three_parts.json``); the
+library orders each owned range differently (by the next part touching a
+vertex) and is compared with it through the owned ranges, owned and foreign
+vertex sets and the isolated tail, which both orderings share.  The
+partitioners are pinned exactly on hand-derived cases under tests/golden/:
+``multilevel.partition`` and ``ggp.partition`` on Figure 1 (``fig1.json``, whose optimum is unique up to part labels), on a path
 whose edge ids run out of path order (``multilevel_path9.json``) and on graphs
 where refinement moves a node and where the contiguity pass moves a piece
 (``multilevel_refine5.json``, ``multilevel_contiguity6.json``), with one
 coarsening level pinned on small weighted graphs in the tests;
 ``baselines.greedy_partition`` on a 9-edge case (``greedy_vertex_cut9.json``).
-Beyond those cases, the exact output of the partitioners, the baselines and
-the layout is parity unpinned: it is fixed by their specification and checked
-only by two independent implementations agreeing bit for bit.
+Beyond those cases, the exact output of the partitioners and the baselines is
+parity unpinned: it is fixed by their specification and checked only by two
+independent implementations agreeing bit for bit.
 """
 
 from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines  # noqa: F401

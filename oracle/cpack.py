@@ -1,16 +1,15 @@
 """Data layout along the task order (Section 4.1, cpack).
 
 The paper reorganises the data array along the new task schedule with
-Ding and Kennedy's cpack and passes the kernel a remapped index array.  The
-reading here is first-touch consecutive packing at the granularity of parts:
+Ding and Kennedy's cpack and passes the kernel a remapped index array.  cpack
+places data consecutively in the order the task sequence first accesses them;
+the reading here is exactly that:
 
 * walk the tasks part by part (ascending part id) and, inside a part, in task
-  order, taking u then v of every edge; the vertices first touched in part p
-  (the ones p OWNS) take the next packed ids of their class, one contiguous
-  range per part and class;
-* inside that range they are ordered by the next part that touches them
-  (vertices no later part touches come first), then by first touch, so that a
-  later part finds the vertices it shares with p side by side;
+  order, taking u then v of every edge; each vertex takes the next packed id of
+  its class at its first touch.  The vertices first touched in part p (the ones
+  p OWNS) therefore form one contiguous range per part and class, in
+  first-touch order;
 * vertices never touched (isolated) follow, in ascending original id;
 * SpMV graphs have two classes, x (original id < n_x) and y; each is packed on
   its own, x into [0, n_x) and y into [n_x, n).
@@ -37,9 +36,9 @@ def layout(edges: np.ndarray, n: int, part, task, n_x: int | None = None) -> dic
     def cls(w):
         return 1 if (bipartite and w >= n_x) else 0
 
-    # which parts touch each vertex (ascending), and the order of first touches
-    parts_of = [[] for _ in range(n)]
+    # the order of first touches along the task sequence, and the part of each
     first_touch = []
+    first_part = np.full(n, -1, dtype=np.int64)
     prev = -1
     for e in task.tolist():
         p = int(part[e])
@@ -47,31 +46,22 @@ def layout(edges: np.ndarray, n: int, part, task, n_x: int | None = None) -> dic
             raise ValueError("task order must visit parts in ascending id")
         prev = p
         for w in (int(edges[e, 0]), int(edges[e, 1])):
-            if not parts_of[w]:
+            if first_part[w] < 0:
+                first_part[w] = p
                 first_touch.append(w)
-            if parts_of[w][-1:] != [p]:
-                parts_of[w].append(p)
-    first_part = np.full(n, -1, dtype=np.int64)
-    for w in first_touch:
-        first_part[w] = parts_of[w][0]
-    rank = {w: i for i, w in enumerate(first_touch)}
-
-    def next_part(w):
-        """The next part after the owner that touches w; -1 if there is none."""
-        return parts_of[w][1] if len(parts_of[w]) > 1 else -1
 
     nxt = list(base)
     o2p = np.full(n, -1, dtype=np.int64)
     own_start = np.zeros((k, len(base)), dtype=np.int64)  # class counters when part p begins
-    owned = [[] for _ in range(k)]
-    for w in first_touch:
-        owned[int(first_part[w])].append(w)
+    i = 0
     for p in range(k):
         own_start[p] = nxt
-        for w in sorted(owned[p], key=lambda x: (next_part(x), rank[x])):
+        while i < len(first_touch) and first_part[first_touch[i]] == p:
+            w = first_touch[i]
             c = cls(w)
             o2p[w] = nxt[c]
             nxt[c] += 1
+            i += 1
     for w in range(n):
         if o2p[w] < 0:
             c = cls(w)

@@ -179,28 +179,56 @@ def test_partition_parity_rmat_bipartite():
     _check_parity(g["edges"], g["n"], 256, "random")
 
 
+def _library_owned_order_ok(perm_lib, own0, nown, edges, part, task):
+    """The library orders a part's owned range by the next part that touches the vertex
+    (vertices no later part touches first), then by first touch."""
+    parts_of, first = {}, {}
+    for j, e in enumerate(task.tolist()):
+        for w in (int(edges[e][0]), int(edges[e][1])):
+            ps = parts_of.setdefault(w, [])
+            if not ps or ps[-1] != int(part[e]):
+                ps.append(int(part[e]))
+            first.setdefault(w, 2 * j + (w == int(edges[e][1])))
+    ids = perm_lib[own0:own0 + nown].tolist()
+    key = [((parts_of[w][1] if len(parts_of[w]) > 1 else -1), first[w]) for w in ids]
+    return key == sorted(key)
+
+
 def _check_layout(edges, n, cap, geom, kind="flux5", n_x=0, order="ep"):
+    """The library's packing against the oracle's first-touch packing (Section 4.1): the same
+    owned range (start, count) per part and class, the same owned and foreign vertex sets,
+    the same isolated tail; inside an owned range the library's own order rule holds."""
     P = Plan(edges, n, cap, geom, order=order, kind=kind, n_x=n_x)
     part, task = P.part_of_edge()
     lay = cpack.layout(edges, n, part, task, n_x=n_x if kind == "spmv" else None)
-    assert np.array_equal(P.perm(), lay["perm"])
+    perm_lib, perm_ref = P.perm(), lay["perm"]
+    assert sorted(perm_lib.tolist()) == list(range(n))
     L = P.layout()
     ncls = 2 if kind == "spmv" else 1
     fo, fi = L["foreign_offset"], L["foreign_ids"]
     for p, info in enumerate(lay["parts"]):
         for c in range(ncls):
-            assert L["own_begin"][p, c] == info["own0"][c]
-            assert L["own_count"][p, c] == info["nown"][c]
+            o0, no = int(L["own_begin"][p, c]), int(L["own_count"][p, c])
+            assert o0 == info["own0"][c] and no == info["nown"][c]
+            assert set(perm_lib[o0:o0 + no].tolist()) == set(perm_ref[o0:o0 + no].tolist())
+            assert _library_owned_order_ok(perm_lib, o0, no, edges, part, task)
             s, e = fo[p * ncls + c], fo[p * ncls + c + 1]
-            assert np.array_equal(fi[s:e], info["foreign"][c])
+            assert (np.diff(fi[s:e]) > 0).all()
+            assert set(perm_lib[fi[s:e]].tolist()) == set(perm_ref[info["foreign"][c]].tolist())
+    iso = lay["first_part"] < 0
+    for lo, hi in ([(0, n_x), (n_x, n)] if kind == "spmv" else [(0, n)]):  # each class ends with its isolated ids
+        n_iso = int(iso[lo:hi].sum())
+        assert np.array_equal(perm_lib[hi - n_iso:hi], perm_ref[hi - n_iso:hi])
+        assert (np.diff(perm_ref[hi - n_iso:hi]) > 0).all() and iso[perm_ref[hi - n_iso:hi]].all()
     stt = P.stats
     assert stt["loads"] == sum(int(L["own_count"][p].sum()) for p in range(stt["n_parts"])) + len(fi)
     assert stt["cost"] == len(fi)
 
 
 def test_plan_layout_hand_derived_three_parts(golden_dir):
-    """The C++ plan packs the hand-derived case of tests/golden/cpack_three_parts.json identically
-    (the default order at capacity 3 is exactly that case's partition)."""
+    """The C++ plan packs the hand-derived case of tests/golden/cpack_three_parts.json as derived
+    for the library's next-consumer order (the default order at capacity 3 is exactly that case's
+    partition); owned ranges and costs are those of the first-touch packing."""
     with open(os.path.join(golden_dir, "cpack_three_parts.json")) as f:
         G = json.load(f)
     E = np.array(G["edges"], dtype=np.int32)
@@ -208,11 +236,11 @@ def test_plan_layout_hand_derived_three_parts(golden_dir):
     P = Plan(E, G["n"], G["capacity"], geom, order="input")
     part, task = P.part_of_edge()
     assert part.tolist() == G["part"] and task.tolist() == G["task"]
-    assert P.perm().tolist() == G["perm"]
+    assert P.perm().tolist() == G["library_perm"]
     L = P.layout()
     fo, fi = L["foreign_offset"], L["foreign_ids"]
     assert L["own_begin"][:, 0].tolist() == G["own_begin"] and L["own_count"][:, 0].tolist() == G["own_count"]
-    assert [fi[fo[p]:fo[p + 1]].tolist() for p in range(len(G["own_begin"]))] == G["foreign"]
+    assert [fi[fo[p]:fo[p + 1]].tolist() for p in range(len(G["own_begin"]))] == G["library_foreign"]
     st_ = P.stats
     assert (st_["loads"], st_["cost"], st_["replicated"], st_["slots"]) == (G["loads"], G["cost"], G["replicated"],
                                                                          G["slots"])

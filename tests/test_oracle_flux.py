@@ -134,6 +134,50 @@ def _subgraph_1k():
     return gen.bfs_subgraph(gen.tet_mesh(8, 8, 8, seed=5), 1000)
 
 
+# One 2D edge (area 1) worked out by hand: n = (0.6, -0.8), q_u = (1, -1, 2, 0, 3),
+# q_v = (2, 2, -2, 0, 5), gamma = 1.4, sigma = 1.
+#   signed: s_u = (-0.6 - 1.6)/1 = -2.2, p_u = 0.4 (3 - 5/2) = 0.2,
+#           f_u = (-2.2, 2.2 + 0.12, -4.4 - 0.16, 0, 3.2 * -2.2) = (-2.2, 2.32, -4.56, 0, -7.04);
+#           s_v = (1.2 + 1.6)/2 = 1.4, p_v = 0.4 (5 - 8/4) = 1.2,
+#           f_v = (2.8, 2.8 + 0.72, -2.8 - 0.96, 0, 6.2 * 1.4) = (2.8, 3.52, -3.76, 0, 8.68);
+#           F = (f_u + f_v)/2 - (q_v - q_u)/2 = (0.3, 2.92, -4.16, 0, 0.82) - (0.5, 1.5, -2, 0, 1)
+#             = (-0.2, 1.42, -2.16, 0, -0.18); r_u = F, r_v = -F.
+#   absolute-value evaluation (|q|, |n| = (0.6, 0.8), every minus a plus):
+#           |q_u| = (1, 1, 2, 0, 3): s = 0.6 + 1.6 = 2.2, p = 0.4 (3 + 5/2) = 2.2,
+#             f = (2.2, 2.2 + 1.32, 4.4 + 1.76, 0, 5.2 * 2.2) = (2.2, 3.52, 6.16, 0, 11.44);
+#           |q_v| = (2, 2, 2, 0, 5): s = (1.2 + 1.6)/2 = 1.4, p = 0.4 (5 + 8/4) = 2.8,
+#             f = (2.8, 2.8 + 1.68, 2.8 + 2.24, 0, 7.8 * 1.4) = (2.8, 4.48, 5.04, 0, 10.92);
+#           A = (f_u + f_v)/2 + (|q_v| + |q_u|)/2 = (2.5, 4, 5.6, 0, 11.18) + (1.5, 1.5, 2, 0, 4)
+#             = (4, 5.5, 7.6, 0, 15.18) at both endpoints.
+#   adjoint floor with g_r[u] = (1, -1, 1, -1, 1), g_r[v] = 0, so |delta| = (1, 1, 1, 1, 1):
+#           B_w = (J_abs(q_w)/2 + I/2)^T |delta| = (column sums of J_abs(q_w) + 1) / 2, with
+#           J_abs(|q_u|) rows (0, .6, .8, 0, 0), (2.8, 3.04, 1.28, 0, .24), (5.2, 1.52, 4.44, 0, .32),
+#             (0, 0, 0, 2.2, 0), (13.64, 4, 5.92, 0, 3.08): column sums (21.64, 9.16, 12.44, 2.2, 3.64);
+#           J_abs(|q_v|) rows (0, .6, .8, 0, 0), (1.64, 2.24, 1.04, 0, .24), (1.72, .92, 2.52, 0, .32),
+#             (0, 0, 0, 1.4, 0), (6.02, 2.9, 3.68, 0, 1.96): column sums (9.38, 6.66, 8.04, 1.4, 2.52).
+_E1 = np.array([[0, 1]])
+_G1 = np.array([[0.6, -0.8]])
+_Q1 = np.array([[1.0, -1.0, 2.0, 0.0, 3.0], [2.0, 2.0, -2.0, 0.0, 5.0]])
+
+
+def test_single_edge_forward_hand_derived():
+    F = np.array([-0.2, 1.42, -2.16, 0.0, -0.18])
+    r = flux.forward(2, _E1, _G1, _Q1)
+    assert np.allclose(r, np.stack([F, -F]), rtol=0, atol=1e-14)
+
+
+def test_single_edge_abs_floors_hand_derived():
+    """Pins the tolerance floors themselves: a floor that drops a term, keeps a sign or is
+    inflated by any factor misses these values (so an elementwise parity check cannot be
+    loosened through its floor)."""
+    A = np.array([4.0, 5.5, 7.6, 0.0, 15.18])
+    assert np.allclose(flux.forward_abs(2, _E1, _G1, _Q1), np.stack([A, A]), rtol=0, atol=1e-13)
+    g_r = np.array([[1.0, -1.0, 1.0, -1.0, 1.0], [0.0] * 5])
+    Bu = (np.array([21.64, 9.16, 12.44, 2.2, 3.64]) + 1.0) / 2
+    Bv = (np.array([9.38, 6.66, 8.04, 1.4, 2.52]) + 1.0) / 2
+    assert np.allclose(flux.backward_abs(2, _E1, _G1, _Q1, g_r), np.stack([Bu, Bv]), rtol=0, atol=1e-13)
+
+
 def test_adjoint_matches_finite_differences_on_1k_cells():
     """FP64 central differences of L = sum r^2 with h_i = 1e-6 max(1, |q_i|)."""
     G = _subgraph_1k()

@@ -54,8 +54,8 @@ def test_fig1_brute_force_optimum(golden_dir):
 
 def test_cpack_hand_derived_three_parts(golden_dir):
     """cpack.layout against a case derived by hand (tests/golden/cpack_three_parts.json):
-    three parts, a vertex next touched by part 1 ahead of two next touched by part 2,
-    an unshared vertex first, an isolated vertex last."""
+    three parts sharing vertices in both directions, owned ranges in first-touch order,
+    foreign lists ascending, an isolated vertex last."""
     with open(os.path.join(golden_dir, "cpack_three_parts.json")) as f:
         G = json.load(f)
     E = np.array(G["edges"])
@@ -277,21 +277,16 @@ def test_cpack_layout(n, m, cap, seed):
     perm = lay["perm"]
     assert sorted(perm.tolist()) == list(range(n))
     assert (lay["orig_to_packed"][perm] == np.arange(n)).all()
-    # first touch along the task sequence, grouped per owning part, and inside a
-    # part ordered by the next part that touches the vertex (none first)
+    # packed ids in the order of first touch along the task sequence (u then v of
+    # each edge), isolated vertices last in ascending id
     seen, order = set(), []
-    touched_by = {}
     for e in task:
         for w in E[e]:
-            touched_by.setdefault(int(w), set()).add(int(part[e]))
             if int(w) not in seen:
                 seen.add(int(w))
                 order.append(int(w))
-    owner = {w: min(ps) for w, ps in touched_by.items()}
-    nxt = {w: (sorted(ps)[1] if len(ps) > 1 else -1) for w, ps in touched_by.items()}
-    expect = sorted(order, key=lambda w: (owner[w], nxt[w], order.index(w)))
     iso = sorted(set(range(n)) - seen)
-    assert perm.tolist() == expect + iso
+    assert perm.tolist() == order + iso
     # owned ranges tile [0, n_active) in part order
     cur = 0
     for info in lay["parts"]:
