@@ -147,6 +147,8 @@ int epk_plan_part_of_edge(const epk_plan *p, int32_t *part_of_edge, int32_t *tas
  * ascending.  Any pointer may be NULL.                                    */
 int epk_plan_layout(const epk_plan *p, int32_t *own_begin, int32_t *own_count, int64_t *foreign_offset,
                     int32_t *foreign_ids);
+/* The plan's partition quality and overhead (Definition 2: loads, cost,
+ * replication; Eq. 1's balance), as epk_partition reports them.          */
 int epk_plan_stats(const epk_plan *p, epk_stats *s);
 /* Kernel-side sizes: [0] = n_parts, [1] = dynamic LDS bytes of the forward,
  * [2] = of the adjoint, [3] = workgroup size, [4] = vertex classes,
@@ -201,18 +203,36 @@ void epk_plan_destroy(epk_plan *p);
 /* ---------------------------------------------------------------- device */
 
 /* FLUX5 forward on packed states: r = sum of a_e F_e over the incident
- * edges (+ at u, - at v) and, if q_new != NULL, q_new = q + dt r.
+ * edges (+ at u, - at v) and, if q_new != NULL, q_new = q + dt r.  The task
+ * is Section 1's cfd interaction (Figure 1: one task per pair of adjacent
+ * particles, reading both and updating both), run in the partition's task
+ * order; each workgroup loads its part's distinct vertices into on-chip
+ * memory with coalesced loads, as Section 4's software-cache kernel does, so
+ * each vertex of a part is fetched once (Definition 2's loads L).
  * q, r, q_new: device [n][5] float32; d_ws: workspace_bytes.  Each
  * workgroup stages its part's vertices in LDS, accumulates per-vertex
  * partials there, writes owned vertices directly and replicated partials to
- * the workspace; a second kernel sums those in ascending part order.     */
+ * the workspace; a second kernel sums those in ascending part order.
+ * EPK_ESTATE before upload or for an SpMV plan, EPK_EINVAL for a NULL
+ * state, output or (when the cost is nonzero) workspace, EPK_EHIP if a
+ * launch fails.                                                           */
 int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream);
-/* FLUX5 adjoint: g_q = (dr/dq)^T g_r, same partition and reduction.      */
+/* FLUX5 adjoint: g_q = (dr/dq)^T g_r on packed q, g_r, g_q (device
+ * [n][5] float32), on the same partition, staging (Section 4) and reduction
+ * as the forward: the upstream gradients are gathered per part like the
+ * states, and each part's vertex-state gradients are summed in LDS.  The
+ * paper has no adjoint; this is the forward's transpose on its schedule.
+ * Errors as epk_forward (g_r must not be NULL).                          */
 int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream);
-/* SPMV: y[n_y] = A x[n_x] in packed x / y ids (y packed id - n_x).        */
+/* SPMV: y[n_y] = A x[n_x] in packed x / y ids (y packed id - n_x), the
+ * paper's sparse-matrix workload (Section 5.2: one vertex per element of x
+ * and of y, one task per nonzero).  x: device [n_x] float32, y: device
+ * [n_y] float32, d_ws: workspace_bytes.  EPK_ESTATE for a FLUX5 plan or
+ * before upload, EPK_EINVAL for NULL buffers.                             */
 int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stream);
-/* The two launches behind epk_forward / epk_backward / epk_spmv, for
- * callers that time or schedule them apart.  stage 0: the part kernel
+/* The two launches behind epk_forward / epk_backward / epk_spmv (Section 4
+ * staging, then the replicated vertices' fixed-order sums), for callers
+ * that time or schedule them apart.  stage 0: the part kernel
  * (owned outputs, workspace partials); stage 1: the reduction (adds the
  * partials of replicated vertices in ascending part order, zeroes untouched
  * vertices, finishes q_new).  Stage 1 must follow stage 0 on the same stream
@@ -221,7 +241,8 @@ int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stre
 int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                   float dt, float *q_new, void *d_ws, void *stream);
 /* op codes of epk_run_stage */
-/* SpMV adjoint on the same plan: g_x = A^T g_y (g_x[j] = sum over the
+/* SpMV adjoint on the same plan (Section 5.2's graph, transposed; the
+ * paper has no adjoint): g_x = A^T g_y (g_x[j] = sum over the
  * nonzeros (i, j) of w g_y[i]) and, if g_w != NULL, the weight gradient
  * g_w[e] = g_y[i] x[j] for every edge e in ORIGINAL edge order.  x: packed
  * [n_x] (only read for g_w; may be NULL otherwise), g_y: packed [n - n_x],
@@ -236,7 +257,10 @@ int epk_spmv_adjoint(const epk_plan *p, const float *x, const float *g_y, float 
 #define EPK_OP_BACKWARD 1
 #define EPK_OP_SPMV 2
 /* dst[i] = src[idx[i]] (inverse = 0) or dst[idx[i]] = src[i] (inverse = 1),
- * rows of ncomp float32; packs states into / out of packed order.         */
+ * rows of ncomp float32 (device, n_rows rows each; idx device int32
+ * [n_rows]); packs states into / out of the packed order, the data layout
+ * transformation that follows the new task order (Section 4.1, cpack).
+ * EPK_EINVAL for NULL buffers or ncomp < 1.                               */
 int epk_permute_rows(const float *src, float *dst, const int32_t *idx, int64_t n_rows, int32_t ncomp,
                      int32_t inverse, void *stream);
 
@@ -266,7 +290,11 @@ void epk_adaptive_destroy(epk_adaptive *a);
 
 /* --------------------------------------------------------------- batched */
 
-/* Many FLUX5 graphs in one launch per pass.  States of graph g live at
+/* Many FLUX5 graphs in one launch per pass: every (graph, part) item is one
+ * workgroup's block of tasks with its data staged as in Section 4, and the
+ * launch shape is the thread-block size that Section 5.2 and Section 5.3
+ * study.  Differs from a per-graph pointer list: the states of all graphs
+ * are one concatenated array.  States of graph g live at
  * rows [vertex_offset(g), vertex_offset(g) + n_g) of one [sum n][5] array,
  * in graph g's packed order.  The plans must be FLUX5 with 4 geometry
  * components; the batch copies what it needs, the plans may be destroyed.
@@ -275,8 +303,11 @@ void epk_adaptive_destroy(epk_adaptive *a);
  * workgroups of one pipelined persistent launch (see epk_plan_set_pipeline;
  * epk_batch_set_launch picks either).                                     */
 int epk_batch_create(int32_t n_graphs, epk_plan *const *plans, epk_batch **out);
+/* Bytes of the batch's device image and workspace (caller-allocated,
+ * 256-byte aligned), as epk_plan_device_bytes.                           */
 int epk_batch_device_bytes(const epk_batch *b, size_t *image_bytes, size_t *workspace_bytes);
-/* Copy the image to d_image and size the grids for the current device.   */
+/* Copy the image to d_image (borrowed for the batch's lifetime) and size
+ * the grids for the current device.                                       */
 int epk_batch_upload(epk_batch *b, void *d_image, void *stream);
 /* Launch shape of the batch.  wg: workgroup size (64..256, multiple of 64,
  * at least capacity / 8; 0 keeps the current one).  direct: 1 runs one
@@ -296,13 +327,18 @@ int epk_batch_vertex_offsets(const epk_batch *b, int64_t *vertex_offset);
  * item (1) or pipelined (0), [9] whether one workgroup per item is
  * possible for this batch.                                                */
 int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info);
+/* Forward / adjoint of every graph of the batch: as epk_forward (dt = 0,
+ * no q_new) and epk_backward, on the concatenated packed states q, r, g_r,
+ * g_q (device [sum n][5] float32) and a workspace of workspace_bytes.  One
+ * part kernel launch and one reduction launch per call.  EPK_ESTATE before
+ * upload, EPK_EINVAL for NULL buffers, EPK_EHIP if a launch fails.        */
 int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream);
 int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws,
                        void *stream);
 void epk_batch_destroy(epk_batch *b);
 
 /* Capacity and launch-shape selection for a batch (the block-size study of
- * Section 5.2, done by measurement): for each capacity in caps[n_caps],
+ * Section 5.2 and Section 5.3, done by measurement on this GPU): for each capacity in caps[n_caps],
  * build every graph's EP plan at that capacity, merge them into one batch
  * and time its forward + adjoint launch (median of 5 timings of 5 passes)
  * in each launch shape: one workgroup per item and the pipelined persistent
