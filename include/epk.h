@@ -134,7 +134,10 @@ int epk_plan_create_partitioned(const epk_graph *g, int32_t capacity, int64_t n_
 /* Bytes of the device image and of the per-call workspace (replicated-vertex
  * partials).  Both are caller-allocated; alignment 256 bytes.             */
 int epk_plan_device_bytes(const epk_plan *p, size_t *image_bytes, size_t *workspace_bytes);
-/* Copy the image to d_image (borrowed for the plan's lifetime) on stream. */
+/* Copy the image to d_image (borrowed for the plan's lifetime) on stream.
+ * The image also holds the single-launch reduction's per-part counters
+ * (zero as uploaded; every launch leaves them zero): calls on one plan that
+ * overlap in time must switch that reduction off (epk_plan_set_fused).    */
 int epk_plan_upload(epk_plan *p, void *d_image, void *stream);
 /* packed_to_orig[n]: original id of each packed vertex id.               */
 int epk_plan_vertex_perm(const epk_plan *p, int32_t *packed_to_orig);
@@ -158,8 +161,9 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s);
  * [9] = max foreign vertices of a part, [10] = pipelined launch setting
  * (0: off), [11] / [12] = its forward / adjoint grid, [13] = its adjoint
  * LDS bytes, [14] = workspace layout in use (0 part-major, 1 vertex-major),
- * [15] = state staging (1 LDS, 0 caches only).  The byte counts follow the
- * layout in use.                                                          */
+ * [15] = state staging (1 LDS, 0 caches only), [16] = single-launch
+ * reduction in use (1) or not (0).  The byte counts follow the layout in
+ * use; with the single launch, [7] / [8] hold the whole pass.             */
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
  * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
@@ -198,6 +202,21 @@ int epk_plan_set_slot_layout(epk_plan *p, int32_t layout);
  * a multiply and an add differently.  Switches the pipelined launch off.
  * EPK_ERANGE if its LDS does not fit.                                     */
 int epk_plan_set_staging(epk_plan *p, int32_t staged);
+/* FLUX5 only: sum the replicated vertices' partials inside the part kernel
+ * (on = 1) or in a second launch (on = 0, the default: on MI355X the
+ * single launch is slower, since the sums' two dependent loads then extend
+ * every workgroup's lifetime instead of running massively parallel).  In the single launch each workgroup stores its replicated
+ * partials at device scope and then signals the part owning each of those
+ * vertices (and itself) with a relaxed device-scope atomic add on that
+ * part's counter (in the plan's image); the workgroup that completes a part's
+ * count sums that part's replicated vertices in ascending part order, the
+ * same arithmetic as the second launch, so results are bitwise the same.
+ * Applies to the direct staged kernels with the part-major workspace (not
+ * to the pipelined or cache-only launches, which keep two launches).
+ * EPK_ESTATE (setting unchanged) if the plan does not allow it: a vertex
+ * with more partials than one thread sums, a part signalling more than 64
+ * parts, or arrays beyond 2 GiB.  Host only.                               */
+int epk_plan_set_fused(epk_plan *p, int32_t on);
 void epk_plan_destroy(epk_plan *p);
 
 /* ---------------------------------------------------------------- device */
@@ -212,7 +231,8 @@ void epk_plan_destroy(epk_plan *p);
  * q, r, q_new: device [n][5] float32; d_ws: workspace_bytes.  Each
  * workgroup stages its part's vertices in LDS, accumulates per-vertex
  * partials there, writes owned vertices directly and replicated partials to
- * the workspace; a second kernel sums those in ascending part order.
+ * the workspace; those are summed in ascending part order, by the
+ * workgroup that completes them or by a second kernel (epk_plan_set_fused).
  * EPK_ESTATE before upload or for an SpMV plan, EPK_EINVAL for a NULL
  * state, output or (when the cost is nonzero) workspace, EPK_EHIP if a
  * launch fails.                                                           */
@@ -236,8 +256,10 @@ int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stre
  * (owned outputs, workspace partials); stage 1: the reduction (adds the
  * partials of replicated vertices in ascending part order, zeroes untouched
  * vertices, finishes q_new).  Stage 1 must follow stage 0 on the same stream
- * with the same buffers.  kind-specific arguments as above; unused ones may
- * be NULL (g_r for forward/spmv, dt/q_new for backward/spmv).            */
+ * with the same buffers.  With the single-launch reduction stage 0 does
+ * both and stage 1 launches nothing.  kind-specific arguments as above;
+ * unused ones may be NULL (g_r for forward/spmv, dt/q_new for
+ * backward/spmv).                                                         */
 int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                   float dt, float *q_new, void *d_ws, void *stream);
 /* op codes of epk_run_stage */

@@ -63,6 +63,14 @@ DevPlan dev_plan(const epk_plan *p) {
   P.max_uy = int32_t(p->max_uy);
   P.max_nf = int32_t(p->max_nf);
   P.n_iso = 0;
+  P.n_slots = int32_t(p->n_slots);
+  if (p->fused_ok) {
+    P.nfy_off = dptr<int32_t>(b, L.nfy_off);
+    P.nfy = dptr<int32_t>(b, L.nfy);
+    P.rsuf = dptr<int32_t>(b, L.rsuf);
+    P.cnt = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(b) + L.cnt);
+    P.max_nfy = int32_t(p->max_nfy);
+  }
   return P;
 }
 
@@ -530,6 +538,16 @@ static int run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *
   hipStream_t s = static_cast<hipStream_t>(stream);
   float *ws = static_cast<float *>(d_ws);
   if (op == EPK_OP_BACKWARD) q_new = nullptr;
+  if (op != EPK_OP_SPMV && fused_in_use(p)) {
+    // single launch: the part kernel also sums the replicated vertices (stage 1 has nothing left)
+    if (stage == 1) return EPK_OK;
+    const hipError_t e =
+        op == EPK_OP_FORWARD
+            ? launch_flux_fwd(P, p->wg, size_t(q_new ? p->lds_fwd_qn : p->lds_fwd), in, out, q_new, dt, ws, p->swizzle,
+                              s, true)
+            : launch_flux_bwd(P, p->wg, size_t(p->lds_bwd), in, g_r, out, ws, p->swizzle, s, true);
+    return e == hipSuccess ? EPK_OK : hip_status(e, "part kernel launch");
+  }
   if (stage != 1) {  // -1 runs both
     hipError_t e = hipSuccess;
     if (op != EPK_OP_SPMV && !p->staging) {

@@ -3,6 +3,7 @@
 
 #include <atomic>
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -71,6 +72,10 @@ struct ImageLayout {
   size_t rvid = 0, roff = 0, sidx = 0, rslot = 0, rrec = 0, heavy = 0, iso = 0, eoff = 0;
   // SpMV adjoint: x incidence per part, y foreign ids, x-class reduction tables
   size_t xinc = 0, xlo = 0, xlofs = 0, rfid = 0, eid = 0, xrvid = 0, xroff = 0, xsidx = 0, xrslot = 0, xheavy = 0;
+  // single-launch reduction (FLUX5): per part, the parts it signals (records {part, target, first
+  // replicated vertex, end} from nfy_off[p] to nfy_off[p + 1]), the first replicated owned vertex,
+  // and one counter per part (zero in the uploaded image and between launches)
+  size_t nfy_off = 0, nfy = 0, rsuf = 0, cnt = 0;
   size_t total = 0;
 };
 
@@ -97,6 +102,10 @@ struct DevPlan {
   const int32_t *eid;    // SpMV adjoint: original edge id of each kernel-order edge
   const int32_t *xsidx;  // SpMV adjoint: x slot of each foreign x (vertex-major x workspace, else NULL)
   const int32_t *eoff;   // [k + 1] first task of every part
+  const int32_t *nfy_off;  // single-launch reduction: [k + 1] first signal record of each part (else NULL)
+  const int32_t *nfy;      // single-launch reduction: [signals][4] {part, target, first, end}
+  const int32_t *rsuf;   // single-launch reduction: local index of each part's first replicated owned vertex
+  int32_t *cnt;          // single-launch reduction: per-part signal counters (in the image)
   int64_t m;          // edge records in the image (FLUX5 plan: k * cap, part p's from p * cap)
   int32_t k;
   int32_t cap;
@@ -109,6 +118,8 @@ struct DevPlan {
   int32_t max_uy;     // SPMV: max y vertices per part
   int32_t max_nf;     // max foreign vertices per part
   int32_t n_iso;      // batch: entries of iso
+  int32_t max_nfy;    // single-launch reduction: most signal records of a part
+  int32_t n_slots;    // workspace rows (replicated partials)
 };
 
 }  // namespace epk
@@ -143,6 +154,9 @@ struct epk_plan {
   // SpMV adjoint's x-class reduction
   int64_t xR = 0, xn_heavy = 0, xn_active = 0, xn_slots = 0;
   bool xvmajor = false;
+  // single-launch reduction (FLUX5): possible for this plan, switched on, signal records per part
+  bool fused_ok = false, fused = false;
+  int64_t max_nfy = 0, n_signals = 0;
   void *d_image = nullptr;
 };
 
@@ -177,6 +191,13 @@ void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its curr
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg);
 int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);
+// The single-launch reduction applies to FLUX5 plans that allow it (part-major workspace, no vertex
+// with more partials than one thread sums) when it is switched on and the direct staged kernels run.
+// The completion list (two int32 per signal record of a part) reuses the kernels' LDS.
+inline bool fused_in_use(const epk_plan *p) {
+  return p->kind == EPK_FLUX5 && p->fused_ok && p->fused && p->staging && !p->pipe && !p->vmajor &&
+         8 * p->max_nfy <= std::min(p->lds_fwd, p->lds_bwd);
+}
 // order < 0: the partition comes from the caller (given_k parts, given_part,
 // given_task as for given_partition).
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status,
@@ -185,6 +206,13 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
 // most kRecSlots) slots, -1 past the last; a first slot of -1 sends the
 // vertex to the slot lists (more slots than a record holds).
 constexpr int kRecSlots = 3;
+constexpr int kMaxSignals = 1024;  // single-launch reduction: parts one part may signal (one lane each)
+#ifndef EPK_CNT_STRIDE
+#define EPK_CNT_STRIDE 32
+#endif
+// single-launch reduction: int32 per part counter (32: one 128-byte line each, so that atomics on
+// different parts' counters never share a line)
+constexpr int kCntStride = EPK_CNT_STRIDE;
 std::vector<int32_t> reduction_records(const std::vector<int32_t> &rvid, const std::vector<int32_t> &roff,
                                        const std::vector<int32_t> &rslot);
 DevPlan dev_plan(const epk_plan *p);

@@ -8,10 +8,11 @@
 namespace epk {
 
 int grid_of_parts(int k, int swizzle);
+// fused: the single-launch reduction (the plan's signal records and counters are set in P)
 hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q, float *r, float *qn, float dt,
-                           float *ws, int swizzle, hipStream_t s);
+                           float *ws, int swizzle, hipStream_t s, bool fused = false);
 hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
-                           int swizzle, hipStream_t s);
+                           int swizzle, hipStream_t s, bool fused = false);
 hipError_t launch_flux_cached(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *out,
                               float *qn, float dt, float *ws, bool backward, int swizzle, hipStream_t s);
 hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, const float *q, const float *gr,

@@ -571,6 +571,47 @@ __device__ __forceinline__ void load_row(const float *src, float *v) {
   }
 }
 
+// ---- device-scope rows (single-launch reduction)
+//
+// A replicated vertex's partials come from several workgroups, possibly on
+// different XCDs, whose L2s are not coherent with one another.  An
+// agent-scope release (an L2 write-back) at the end of every part made the
+// part kernels about 12x slower on tet55, so the partials that another
+// workgroup sums within the same launch move through device-scope accesses
+// instead: buffer stores with the device-scope cache policy (sc1) write
+// through the XCD's L2 to the device's coherence point, and device-scope
+// loads read from it.  Rows are addressed by 32-bit byte offsets inside a
+// buffer resource covering the array.
+constexpr int kDeviceScope = 16;  // cache-policy operand of a buffer access: sc1, device scope
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// An array of rows for device-scope access (NULL base: not used).
+struct DevRows {
+  const float *base;
+  int64_t rows;
+};
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(DevRows a) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a.base), 0, int(a.rows * 20), 0x00020000);
+}
+__device__ __forceinline__ void store_row_dev(DevRows a, int64_t row, const float *v) {
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(a);
+  const int o = int(row * 20);
+  const f32x4 x = {v[0], v[1], v[2], v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(x, rs, o, 0, kDeviceScope);
+  // the 32-bit buffer builtins move an integer: pass the float's bits, not its value
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[4]), rs, o + 16, 0, kDeviceScope);
+}
+__device__ __forceinline__ void load_row_dev(DevRows a, int64_t row, float *v) {
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(a);
+  const int o = int(row * 20);
+  const f32x4 x = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, kDeviceScope);
+  v[4] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, o + 16, 0, kDeviceScope));
+  v[0] = x.x;
+  v[1] = x.y;
+  v[2] = x.z;
+  v[3] = x.w;
+}
+
 // The destination row of local vertex i's sum: owned vertices go to out (row
 // own0 + i), foreign ones to their workspace slot.
 __device__ __forceinline__ float *sum_row(const PartHdr &h, const int32_t *sidx, float *out, float *ws, int i) {
@@ -582,14 +623,28 @@ __device__ __forceinline__ float *sum_row(const PartHdr &h, const int32_t *sidx,
 // Per-vertex forward sums, each lane storing its vertex's row from registers
 // (owned: r and q_new; foreign: the slot), so no LDS round trip or barrier
 // follows the sums.
-template <bool QNEW>
+// FUSED (single-launch reduction, part-major workspace): local vertices from
+// rsuf on are replicated (the owned ones, then the foreign ones); their rows
+// are stored at device scope for the workgroup that will sum them, and the
+// q_new of replicated owned vertices is left to that workgroup.
+template <bool QNEW, bool FUSED = false>
 __device__ __forceinline__ void sum_store_fwd(const PartHdr &h, const float *st, const float *flx, const uint16_t *inc,
                                               const uint16_t *lo, const int32_t *sidx, float *__restrict__ r,
                                               float *__restrict__ qn, float dt, float *__restrict__ ws, int tid,
-                                              int nt) {
+                                              int nt, int rsuf = 0, DevRows rr = {nullptr, 0},
+                                              DevRows rw = {nullptr, 0}) {
   for (int i = tid; i < h.U; i += nt) {
     float s[5];
     vertex_sum_fwd(flx, inc, lo, i, s);
+    if constexpr (FUSED) {
+      if (i >= rsuf) {
+        if (i < h.nown)
+          store_row_dev(rr, int64_t(h.own0) + i, s);
+        else
+          store_row_dev(rw, int64_t(h.f0) + (i - h.nown), s);
+        continue;
+      }
+    }
     store_row(sum_row(h, sidx, r, ws, i), s);
     if constexpr (QNEW) {
       if (i < h.nown) {
@@ -603,14 +658,182 @@ __device__ __forceinline__ void sum_store_fwd(const PartHdr &h, const float *st,
 }
 
 // Adjoint counterpart: owned sums to gq, foreign ones to their slots.
+template <bool FUSED = false>
 __device__ __forceinline__ void sum_store_bwd(const PartHdr &h, const float *vu, const float *vv, const uint16_t *inc,
                                               const uint16_t *lo, const int32_t *sidx, float *__restrict__ gq,
-                                              float *__restrict__ ws, int tid, int nt) {
+                                              float *__restrict__ ws, int tid, int nt, int rsuf = 0,
+                                              DevRows rr = {nullptr, 0}, DevRows rw = {nullptr, 0}) {
   for (int i = tid; i < h.U; i += nt) {
     float s[5];
     vertex_sum_bwd(vu, vv, inc, lo, i, s);
+    if constexpr (FUSED) {
+      if (i >= rsuf) {
+        if (i < h.nown)
+          store_row_dev(rr, int64_t(h.own0) + i, s);
+        else
+          store_row_dev(rw, int64_t(h.f0) + (i - h.nown), s);
+        continue;
+      }
+    }
     store_row(sum_row(h, sidx, gq, ws, i), s);
   }
+}
+
+// ---- reduction of one light replicated vertex
+//
+// r_v = (((own + s_1) + s_2) + ...) over at most kHeavySlots partials in
+// ascending part order, then q_new.  A part-major workspace lists a vertex's
+// slots in its record (up to kRecSlots) or through rslot; a vertex-major one
+// keeps them as one run.  DEV: the owner partial and the slots are read at
+// device scope (the single-launch reduction sums partials that other
+// workgroups stored in the same launch).  The reduction kernel and the
+// single-launch reduction share this function, so their sums agree bit for bit.
+template <int NC, bool QNEW, bool DEV>
+__device__ __forceinline__ void reduce_light(const DevPlan &P, int64_t rho, float *__restrict__ r,
+                                             const float *__restrict__ ws, const float *__restrict__ q,
+                                             float *__restrict__ qn, float dt, DevRows rr, DevRows rw) {
+  auto ld_r = [&](int64_t row, float *v) {
+    if constexpr (DEV)
+      load_row_dev(rr, row, v);
+    else
+      load_row<NC>(r + row * NC, v);
+  };
+  auto ld_w = [&](int64_t row, float *v) {
+    if constexpr (DEV)
+      load_row_dev(rw, row, v);
+    else
+      load_row<NC>(ws + row * NC, v);
+  };
+  // The whole record is read before the branch on it, so that the rows are
+  // the second and last dependent load of the record path.
+  int4 rec = make_int4(-1, -1, -1, -1);
+  if (P.rrec) rec = reinterpret_cast<const int4 *>(P.rrec)[rho];
+  int64_t o;
+  float s[NC];
+  if (rec.y >= 0) {
+    // up to kRecSlots slots, all in the vertex's record: one dependent load
+    // fewer than the slot lists; absent slots re-read the first with
+    // weight 0 (the sum's bits are those of the list path)
+    o = int64_t(rec.x);
+    const int sl[3] = {rec.y, rec.z, rec.w};
+    float v[3][NC];
+    ld_r(o, s);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) ld_w(int64_t(sl[u] < 0 ? rec.y : sl[u]), v[u]);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const float w = sl[u] < 0 ? 0.f : 1.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
+    }
+  } else {
+    const int s0 = P.roff[rho], s1 = P.roff[rho + 1];
+    if (s1 - s0 > kHeavySlots) return;
+    o = int64_t(P.rvid[rho]);
+    ld_r(o, s);
+    if (P.rslot) {
+      for (int t = s0; t < s1; t += 4) {
+        // four slots per batch of loads, with no branch: past the vertex's
+        // last slot, its first slot is read again with weight 0 (adding
+        // zero leaves the sum's bits unchanged)
+        int in[4], sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) in[u] = -int(t + u < s1);
+        asm volatile("" : "+v"(in[0]), "+v"(in[1]), "+v"(in[2]), "+v"(in[3]));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sl[u] = P.rslot[s0 + ((t + u - s0) & in[u])];
+        float v[4][NC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ld_w(int64_t(sl[u]), v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float w = __int_as_float(0x3f800000 & in[u]);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
+        }
+      }
+    } else {
+      for (int t = s0; t < s1; ++t) {
+        float v[NC];
+        ld_w(int64_t(t), v);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] += v[c];
+      }
+    }
+  }
+  store_row<NC>(r + o * NC, s);
+  if constexpr (QNEW) {
+    float qv[NC], t[NC];
+    load_row<NC>(q + o * NC, qv);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = qv[c] + dt * s[c];
+    store_row<NC>(qn + o * NC, t);
+  }
+}
+
+// ---- single-launch reduction, at the end of a direct part kernel
+//
+// Part p signals itself (if it owns replicated vertices) and the owner of
+// each of its foreign vertices: one relaxed device-scope atomic add on that
+// part's counter, by lane t for p's t-th signal record {part q, target, q's
+// first replicated vertex, end}.  Before it, every wave has waited for its
+// own stores, which the device-scope ones complete at the device's coherence
+// point.  A part's target counts the parts that signal it, so the workgroup
+// that brings q's counter to its target comes after every partial of q's
+// replicated vertices: it sums them (reduce_light, with device-scope loads)
+// and sets the counter back to zero for the next launch.  Untouched vertices
+// (past n_active) are zeroed part by part, a slice each.  n_done: an LDS
+// counter set to zero before the kernel's first barrier.
+__device__ __forceinline__ void signal_one(const DevPlan &P, int4 sig, int32_t *lds, int32_t *n_done) {
+  if (sig.x < 0) return;
+  int32_t *c = P.cnt + int64_t(sig.x) * kCntStride;
+  const int old = __hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (old == sig.y - 1) {
+    __hip_atomic_store(c, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int at = atomicAdd(n_done, 1);
+    lds[2 * at] = sig.z;
+    lds[2 * at + 1] = sig.w;
+  }
+}
+
+// sig: lane tid's record (loaded with the rows); records past the first nt
+// (parts signalling more parts than the workgroup has lanes) are read here.
+template <bool QNEW>
+__device__ __forceinline__ void fused_reduce(const DevPlan &P, int part, int4 sig, int s0, int s1,
+                                             float *__restrict__ r, float *__restrict__ qn,
+                                             const float *__restrict__ q, float dt, const float *__restrict__ ws,
+                                             int32_t *lds, int32_t *n_done, DevRows rr, DevRows rw, int tid, int nt) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are complete
+  __syncthreads();                                   // ... and every other wave's; LDS is free again
+  signal_one(P, sig, lds, n_done);
+  for (int t = tid + nt; t < s1 - s0; t += nt) signal_one(P, reinterpret_cast<const int4 *>(P.nfy)[s0 + t], lds, n_done);
+  __syncthreads();
+  const int nd = *n_done;
+  for (int d = 0; d < nd; ++d) {
+    const int b = lds[2 * d], e = lds[2 * d + 1];
+    for (int j = b + tid; j < e; j += nt) reduce_light<5, QNEW, true>(P, j, r, ws, q, qn, dt, rr, rw);
+  }
+  const int n_iso = P.n - P.n_active;
+  if (n_iso > 0) {
+    const int per = (n_iso + P.k - 1) / P.k;
+    const int v0 = P.n_active + part * per, v1 = min(P.n, v0 + per);
+    for (int v = v0 + tid; v < v1; v += nt) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        r[int64_t(v) * 5 + c] = 0.0f;
+        if constexpr (QNEW) qn[int64_t(v) * 5 + c] = q[int64_t(v) * 5 + c];
+      }
+    }
+  }
+}
+
+// Signal records of a part for the single-launch reduction: lane t holds the
+// t-th (part -1 past the last).  Issued after the header wait, next to the
+// row gathers, so that it lands with them.
+__device__ __forceinline__ int4 load_signal(const DevPlan &P, int s0, int s1, int tid) {
+  int4 sig = make_int4(-1, 0, 0, 0);
+  if (tid < s1 - s0) sig = reinterpret_cast<const int4 *>(P.nfy)[s0 + tid];
+  return sig;
 }
 
 // ---- direct kernels: one part per workgroup
@@ -618,7 +841,7 @@ __device__ __forceinline__ void sum_store_bwd(const PartHdr &h, const float *vu,
 // LDS: st[max_u][5] | flx[cap][5] (the ids until the flux stage) |
 // inc[2 cap] u16 | lo[nlo] u16 | (vertex-major workspace: sidx[max_nf]),
 // nlo = max_u + 2 rounded up to even.  The sums leave from registers.
-template <int G, bool QNEW, int EPT>
+template <int G, bool QNEW, int EPT, bool FUSED = false>
 __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *__restrict__ q, float *__restrict__ r,
                                                         float *__restrict__ qn, float dt, float *__restrict__ ws,
                                                         int swizzle) {
@@ -626,6 +849,14 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
   const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ int32_t n_done;
+  int s0 = 0, s1 = 0, rsuf = 0;
+  if constexpr (FUSED) {
+    s0 = P.nfy_off[part];
+    s1 = P.nfy_off[part + 1];
+    rsuf = P.rsuf[part];
+    if (tid == 0) n_done = 0;
+  }
   float *st = smem;
   float *flx = st + P.max_u * 5;
   uint16_t *inc = reinterpret_cast<uint16_t *>(flx + P.cap * 5);
@@ -648,14 +879,23 @@ __global__ void __launch_bounds__(1024) flux_fwd_kernel(DevPlan P, const float *
            reinterpret_cast<float *>(sidx), P.sidx ? reinterpret_cast<const float *>(P.sidx + h.f0) : nullptr,
            P.sidx ? h.nf : 0, tid, nt);
   dma_rows<5>(st + h.nown * 5, q, ids, h.nf, tid, nt);
+  int4 sig = make_int4(-1, 0, 0, 0);
+  if constexpr (FUSED) sig = load_signal(P, s0, s1, tid);
   wait_staged();
   edge_stage_fwd<G, EPT>(h, st, flx, ew, eg, tid, nt);
-  sum_store_fwd<QNEW>(h, st, flx, inc, lo, P.sidx ? sidx : nullptr, r, qn, dt, ws, tid, nt);
+  if constexpr (FUSED) {
+    const DevRows rr = {r, P.n}, rw = {ws, P.n_slots};
+    sum_store_fwd<QNEW, true>(h, st, flx, inc, lo, nullptr, r, qn, dt, ws, tid, nt, rsuf, rr, rw);
+    fused_reduce<QNEW>(P, part, sig, s0, s1, r, qn, q, dt, ws, reinterpret_cast<int32_t *>(smem), &n_done, rr, rw, tid,
+                       nt);
+  } else {
+    sum_store_fwd<QNEW>(h, st, flx, inc, lo, P.sidx ? sidx : nullptr, r, qn, dt, ws, tid, nt);
+  }
 }
 
 // LDS: st[max_u][5] | gs[max_u][5] | vu[cap][5] (the ids until the flux
 // stage) | vv[cap][5] | inc | lo | sidx.
-template <int G, int EPT>
+template <int G, int EPT, bool FUSED = false>
 __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *__restrict__ q,
                                                         const float *__restrict__ gr, float *__restrict__ gq,
                                                         float *__restrict__ ws, int swizzle) {
@@ -663,6 +903,14 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
   const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ int32_t n_done;
+  int s0 = 0, s1 = 0, rsuf = 0;
+  if constexpr (FUSED) {
+    s0 = P.nfy_off[part];
+    s1 = P.nfy_off[part + 1];
+    rsuf = P.rsuf[part];
+    if (tid == 0) n_done = 0;
+  }
   float *st = smem;
   float *gs = st + P.max_u * 5;
   float *vu = gs + P.max_u * 5;
@@ -685,9 +933,18 @@ __global__ void __launch_bounds__(1024) flux_bwd_kernel(DevPlan P, const float *
            nt);
   dma_block2(st, q + int64_t(h.own0) * 5, gs, gr + int64_t(h.own0) * 5, h.nown * 5, tid, nt);
   dma_rows2<5>(st + h.nown * 5, q, gs + h.nown * 5, gr, ids, h.nf, tid, nt);
+  int4 sig = make_int4(-1, 0, 0, 0);
+  if constexpr (FUSED) sig = load_signal(P, s0, s1, tid);
   wait_staged();
   edge_stage_bwd<G, EPT>(h, st, gs, vu, vv, ew, eg, tid, nt);
-  sum_store_bwd(h, vu, vv, inc, lo, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
+  if constexpr (FUSED) {
+    const DevRows rr = {gq, P.n}, rw = {ws, P.n_slots};
+    sum_store_bwd<true>(h, vu, vv, inc, lo, nullptr, gq, ws, tid, nt, rsuf, rr, rw);
+    fused_reduce<false>(P, part, sig, s0, s1, gq, nullptr, nullptr, 0.f, ws, reinterpret_cast<int32_t *>(smem),
+                        &n_done, rr, rw, tid, nt);
+  } else {
+    sum_store_bwd(h, vu, vv, inc, lo, P.sidx ? sidx : nullptr, gq, ws, tid, nt);
+  }
 }
 
 // ---- cache-only kernels: no LDS staging of states
@@ -1166,12 +1423,9 @@ __global__ void __launch_bounds__(1024) spmv_adj_kernel(DevPlan P, const float *
 
 // ------------------------------------------------------------------ reduction
 
-// Light vertices (<= kHeavySlots partials): one thread per vertex,
-// r_v = (((own + s_1) + s_2) + ...) in ascending part order; a vertex's slots
-// are one contiguous run of a vertex-major workspace, or, in a part-major
-// one, listed in its record (up to kRecSlots) or found through rslot.  Heavy vertices: one workgroup
-// each, strided partial sums then a fixed tree.  Untouched vertices are
-// zeroed here as well.
+// Light vertices (<= kHeavySlots partials): one thread per vertex
+// (reduce_light).  Heavy vertices: one workgroup each, strided partial sums
+// then a fixed tree.  Untouched vertices are zeroed here as well.
 template <int NC, bool QNEW>
 __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restrict__ r, const float *__restrict__ ws,
                                                      const float *__restrict__ q, float *__restrict__ qn, float dt,
@@ -1179,78 +1433,8 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevPlan P, float *__restric
   __shared__ float red[kHeavyBlock];
   if (int(blockIdx.x) < nb_light) {
     const int64_t rho = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    // The whole record is read before the branch on it, so that the rows are
-    // the second and last dependent load of the record path.
-    int4 rec = make_int4(-1, -1, -1, -1);
-    if (rho < P.R && P.rrec) rec = reinterpret_cast<const int4 *>(P.rrec)[rho];
-    if (rec.y >= 0) {
-      // up to kRecSlots slots, all in the vertex's record: one dependent load
-      // fewer than the slot lists; absent slots re-read the first with
-      // weight 0 (the sum's bits are those of the list path)
-      const int64_t o = int64_t(rec.x) * NC;
-      const int sl[3] = {rec.y, rec.z, rec.w};
-      float s[NC], v[3][NC];
-      load_row<NC>(r + o, s);
-#pragma unroll
-      for (int u = 0; u < 3; ++u) load_row<NC>(ws + int64_t(sl[u] < 0 ? rec.y : sl[u]) * NC, v[u]);
-#pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const float w = sl[u] < 0 ? 0.f : 1.f;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
-      }
-      store_row<NC>(r + o, s);
-      if constexpr (QNEW) {
-        float qv[NC], t[NC];
-        load_row<NC>(q + o, qv);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) t[c] = qv[c] + dt * s[c];
-        store_row<NC>(qn + o, t);
-      }
-    } else if (rho < P.R) {
-      const int s0 = P.roff[rho], s1 = P.roff[rho + 1];
-      if (s1 - s0 > kHeavySlots) return;
-      const int64_t o = int64_t(P.rvid[rho]) * NC;
-      float s[NC];
-      load_row<NC>(r + o, s);
-      if (P.rslot) {
-        for (int t = s0; t < s1; t += 4) {
-          // four slots per batch of loads, with no branch: past the vertex's
-          // last slot, its first slot is read again with weight 0 (adding
-          // zero leaves the sum's bits unchanged)
-          int in[4], sl[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) in[u] = -int(t + u < s1);
-          asm volatile("" : "+v"(in[0]), "+v"(in[1]), "+v"(in[2]), "+v"(in[3]));
-#pragma unroll
-          for (int u = 0; u < 4; ++u) sl[u] = P.rslot[s0 + ((t + u - s0) & in[u])];
-          float v[4][NC];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) load_row<NC>(ws + int64_t(sl[u]) * NC, v[u]);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const float w = __int_as_float(0x3f800000 & in[u]);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) s[c] += w * v[u][c];
-          }
-        }
-      } else {
-        const float *wp = ws + int64_t(s0) * NC;
-        for (int t = 0; t < s1 - s0; ++t) {
-          float v[NC];
-          load_row<NC>(wp + t * NC, v);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) s[c] += v[c];
-        }
-      }
-      store_row<NC>(r + o, s);
-      if constexpr (QNEW) {
-        float qv[NC], t[NC];
-        load_row<NC>(q + o, qv);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) t[c] = qv[c] + dt * s[c];
-        store_row<NC>(qn + o, t);
-      }
+    if (rho < P.R) {
+      reduce_light<NC, QNEW, false>(P, rho, r, ws, q, qn, dt, {nullptr, 0}, {nullptr, 0});
     } else if (rho < int64_t(P.R) + (P.iso ? P.n_iso : P.n - P.n_active)) {
       const int64_t v = P.iso ? int64_t(P.iso[rho - P.R]) : int64_t(P.n_active) + (rho - P.R);
 #pragma unroll
@@ -1324,41 +1508,44 @@ int edges_per_thread(int cap, int wg) {
       return hipErrorInvalidValue; \
   }
 
+// fused: the single-launch reduction (P.nfy_off, P.nfy, P.rsuf and P.cnt set).
 hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q, float *r, float *qn, float dt,
-                           float *ws, int swizzle, hipStream_t s) {
+                           float *ws, int swizzle, hipStream_t s, bool fused) {
   if (P.k == 0) return hipSuccess;
   const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
   const int ept = edges_per_thread(P.cap, wg);
+#define EPK_FWD(G, QN, F) \
+  EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<G, QN, E, F>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle))
   if (P.geom_ncomp == 4) {
     if (qn) {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<4, true, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
-                                             swizzle))
+      if (fused) { EPK_FWD(4, true, true) } else { EPK_FWD(4, true, false) }
     } else {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<4, false, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
-                                             swizzle))
+      if (fused) { EPK_FWD(4, false, true) } else { EPK_FWD(4, false, false) }
     }
   } else {
     if (qn) {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<2, true, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
-                                             swizzle))
+      if (fused) { EPK_FWD(2, true, true) } else { EPK_FWD(2, true, false) }
     } else {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<2, false, E>), grid, block, lds, s, P, q, r, qn, dt, ws,
-                                             swizzle))
+      if (fused) { EPK_FWD(2, false, true) } else { EPK_FWD(2, false, false) }
     }
   }
+#undef EPK_FWD
   return hipGetLastError();
 }
 
 hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q, const float *gr, float *gq, float *ws,
-                           int swizzle, hipStream_t s) {
+                           int swizzle, hipStream_t s, bool fused) {
   if (P.k == 0) return hipSuccess;
   const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
   const int ept = edges_per_thread(P.cap, wg);
+#define EPK_BWD(G, F) \
+  EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<G, E, F>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
   if (P.geom_ncomp == 4) {
-    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<4, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
+    if (fused) { EPK_BWD(4, true) } else { EPK_BWD(4, false) }
   } else {
-    EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<2, E>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
+    if (fused) { EPK_BWD(2, true) } else { EPK_BWD(2, false) }
   }
+#undef EPK_BWD
   return hipGetLastError();
 }
 

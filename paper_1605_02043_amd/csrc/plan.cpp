@@ -467,6 +467,60 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->xvmajor = P->xn_slots > 4 * P->xR;
     }
 
+    // ---- single-launch reduction (FLUX5, part-major): the workgroup that completes the last
+    // partial of a part's replicated vertices sums them.  Part p signals itself (if it owns
+    // replicated vertices) and the owner of each of its foreign vertices; a part's target is the
+    // number of parts that signal it.  The library's packing puts a part's replicated owned
+    // vertices at the end of its owned range, so its owner partials are a known suffix.
+    std::vector<int32_t> nfy_off, nfy_flat, rsuf;
+    if (kind == EPK_FLUX5 && k > 0) {
+      std::vector<int32_t> rbeg(size_t(k) + 1, 0), owner(size_t(n), -1), target(size_t(k), 0);
+      std::vector<std::vector<int32_t>> sig(static_cast<size_t>(k));
+      bool ok = P->n_heavy == 0 && int64_t(n) * 20 < (int64_t(1) << 31) &&
+                int64_t(red_foreign.size()) * 20 < (int64_t(1) << 31);
+      rsuf.assign(size_t(k), 0);
+      for (int64_t q = 0; q < k; ++q) {
+        const int32_t o0 = P->own_begin[q], no = P->own_count[q];
+        for (int32_t i = 0; i < no; ++i) owner[o0 + i] = int32_t(q);
+        rbeg[q] = int32_t(std::lower_bound(rvid.begin(), rvid.end(), o0) - rvid.begin());
+        const int32_t re = int32_t(std::lower_bound(rvid.begin(), rvid.end(), o0 + no) - rvid.begin());
+        const int32_t nrep = re - rbeg[q];
+        rsuf[q] = no - nrep;
+        for (int32_t j = 0; j < nrep && ok; ++j) ok = rvid[rbeg[q] + j] == o0 + rsuf[q] + j;
+        if (nrep > 0) sig[q].push_back(int32_t(q));
+      }
+      rbeg[k] = int32_t(rvid.size());
+      for (int64_t p2 = 0; p2 < k && ok; ++p2) {
+        const int32_t *h = &hdr[size_t(p2) * kHdrInts];
+        for (int32_t f = 0; f < h[5]; ++f) sig[p2].push_back(owner[fid[size_t(h[4] + f)]]);
+        std::sort(sig[p2].begin(), sig[p2].end());
+        sig[p2].erase(std::unique(sig[p2].begin(), sig[p2].end()), sig[p2].end());
+        for (int32_t q : sig[p2]) ok = ok && q >= 0 && q <= p2;  // owners come first in the task order
+        if (ok) for (int32_t q : sig[p2]) target[q]++;
+        P->n_signals += int64_t(sig[p2].size());
+        P->max_nfy = std::max<int64_t>(P->max_nfy, int64_t(sig[p2].size()));
+      }
+      ok = ok && P->max_nfy <= kMaxSignals;
+      P->fused_ok = ok;
+      P->fused = false;  // measured slower than the reduction launch on gfx950: opt-in
+      if (ok) {
+        nfy_off.assign(size_t(k) + 1, 0);
+        for (int64_t p2 = 0; p2 < k; ++p2) {
+          nfy_off[p2 + 1] = nfy_off[p2] + int32_t(sig[p2].size());
+          for (int32_t q : sig[p2]) {
+            nfy_flat.push_back(q);
+            nfy_flat.push_back(target[q]);
+            nfy_flat.push_back(rbeg[q]);
+            nfy_flat.push_back(rbeg[q + 1]);
+          }
+        }
+      } else {
+        rsuf.clear();
+        P->max_nfy = 0;
+        P->n_signals = 0;
+      }
+    }
+
     // ---- device image
     ImageLayout &L = P->lay;
     size_t off = 0;
@@ -511,6 +565,10 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     L.xrslot = take(xrslot.size() * 4);
     L.xheavy = take(xheavy.size() * 4);
     L.heavy = take(heavy.size() * 4);
+    L.nfy_off = take(nfy_off.size() * 4);
+    L.nfy = take(nfy_flat.size() * 4);
+    L.rsuf = take(rsuf.size() * 4);
+    L.cnt = take(rsuf.empty() ? 0 : size_t(k) * 4 * kCntStride);  // zero in the image
     L.total = std::max<size_t>(off, 256);
     P->image.assign(L.total, 0);
     put(P->image, L.eoff, eoff);
@@ -540,6 +598,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       put(P->image, L.xheavy, xheavy);
     }
     put(P->image, L.heavy, heavy);
+    put(P->image, L.nfy_off, nfy_off);
+    put(P->image, L.nfy, nfy_flat);
+    put(P->image, L.rsuf, rsuf);
     const int nc = kind == EPK_SPMV ? 1 : 5;
     // the SpMV adjoint's x partials share the workspace (one launch pair at a time)
     P->ws_bytes = align256(std::max<size_t>(std::max(red_foreign.size() * nc, size_t(P->xn_slots)) * 4, 4));
@@ -661,23 +722,37 @@ int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info) {
   epk::clear_error();
   if (!p || !info) return epk::fail(EPK_EINVAL, "NULL argument");
   const int64_t bf = epk::plan_bytes(p, 0), bb = epk::plan_bytes(p, 1), br = epk::plan_bytes(p, 2);
-  const int64_t v[16] = {p->k,
+  // the single launch moves the reduction's bytes plus its signals (a 16-byte record read and a
+  // 4-byte counter read and written per signal)
+  const bool fu = epk::fused_in_use(p);
+  const int64_t sig = 24 * p->n_signals;
+  const int64_t v[17] = {p->k,
                          p->lds_fwd,
                          p->lds_bwd,
                          p->wg,
                          p->ncls,
-                         bf + br,
-                         p->kind == EPK_FLUX5 ? bb + br : 0,
-                         bf,
-                         bb,
+                         bf + br + (fu ? sig : 0),
+                         p->kind == EPK_FLUX5 ? bb + br + (fu ? sig : 0) : 0,
+                         fu ? bf + br + sig : bf,
+                         fu ? bb + br + sig : bb,
                          p->max_nf,
                          p->pipe,
                          p->pipe ? p->grid_pipe_fwd : 0,
                          p->pipe ? p->grid_pipe_bwd : 0,
                          p->lds_pipe_bwd,
                          p->vmajor ? 1 : 0,
-                         p->staging};
-  for (int32_t i = 0; i < n_info && i < 16; ++i) info[i] = v[i];
+                         p->staging,
+                         fu ? 1 : 0};
+  for (int32_t i = 0; i < n_info && i < 17; ++i) info[i] = v[i];
+  return EPK_OK;
+}
+
+int epk_plan_set_fused(epk_plan *p, int32_t on) {
+  epk::clear_error();
+  if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
+  if (on != 0 && on != 1) return epk::fail(EPK_EINVAL, "on must be 0 or 1");
+  if (on && !p->fused_ok) return epk::fail(EPK_ESTATE, "this plan cannot sum its replicated vertices in one launch");
+  p->fused = on == 1;
   return EPK_OK;
 }
 

@@ -147,11 +147,11 @@ class Plan:
         return st.as_dict()
 
     def info(self) -> dict:
-        a = np.zeros(16, dtype=np.int64)
-        check(lib.epk_plan_info(self._h, i64p(a), 16))
+        a = np.zeros(17, dtype=np.int64)
+        check(lib.epk_plan_info(self._h, i64p(a), 17))
         keys = ["n_parts", "lds_fwd", "lds_bwd", "wg", "ncls", "bytes_fwd", "bytes_bwd", "bytes_fwd_kernel",
                 "bytes_bwd_kernel", "max_nf", "pipe", "grid_pipe_fwd", "grid_pipe_bwd", "lds_pipe_bwd",
-                "vertex_major", "staging"]
+                "vertex_major", "staging", "fused"]
         return dict(zip(keys, a.tolist()))
 
     def perm(self) -> np.ndarray:
@@ -193,6 +193,10 @@ class Plan:
     def set_slot_layout(self, layout: int = -1):
         """Workspace layout of the replicated partials: 0 part-major, 1 vertex-major, -1 automatic."""
         check(lib.epk_plan_set_slot_layout(self._h, int(layout)))
+
+    def set_fused(self, on: int = 1):
+        """FLUX5: sum replicated vertices inside the part kernel (1) or in a second launch (0)."""
+        check(lib.epk_plan_set_fused(self._h, int(on)))
 
     def set_pipeline(self, blocks_per_cu: int = -1):
         """FLUX5: pipelined persistent launch with blocks_per_cu workgroups per CU (-1: as many as

@@ -317,7 +317,7 @@ def test_slot_layout_choice_and_bytes():
     its id and offsets (4 R + 4 (R + 1)); mesh vertices never have more than the
     record's three slots, so no slot list is read."""
     T = gen.tet_mesh(8, 8, 8, seed=0)
-    P = Plan(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
+    P = Plan(T["edges"], T["n"], 128, T["geom"].astype(np.float32))  # two launches (the default)
     st = P.stats
     R, C = st["replicated"], st["cost"]
     a = P.info()
@@ -429,3 +429,61 @@ def test_binding_checks_device_buffers():
             B.backward(b, good)
         with pytest.raises(ValueError):
             B.backward(good, good, out=b)
+
+
+def _signals(P):
+    """Signal records of the single-launch reduction, recounted from the plan's layout: each part
+    signals the owner of every foreign vertex, and itself if a later part uses one of its vertices."""
+    L = P.layout()
+    k = P.stats["n_parts"]
+    ob, oc, fo, fi = L["own_begin"][:, 0], L["own_count"][:, 0], L["foreign_offset"], L["foreign_ids"]
+    owner = np.full(P.n, -1)
+    for q in range(k):
+        owner[ob[q]:ob[q] + oc[q]] = q
+    shared = np.zeros(P.n, bool)
+    shared[fi] = True
+    sig = [set(owner[fi[fo[p]:fo[p + 1]]].tolist()) | ({p} if shared[ob[p]:ob[p] + oc[p]].any() else set())
+           for p in range(k)]
+    return sig
+
+
+def test_single_launch_reduction_accounting_and_switch():
+    """FLUX5 mesh plans can sum their replicated vertices inside the part kernel (off by
+    default).  Its bytes are the two launches' plus 24 per signal (a 16-byte record, a 4-byte
+    counter read and written); switching it off restores the two-launch figures; the
+    vertex-major layout, the pipelined and the cache-only launches keep two launches; SpMV
+    plans cannot switch it on."""
+    T = gen.tet_mesh(8, 8, 8, seed=0)
+    P = Plan(T["edges"], T["n"], 128, T["geom"].astype(np.float32))
+    assert P.info()["fused"] == 0
+    P.set_fused(1)
+    a = P.info()
+    assert a["fused"] == 1
+    n_sig = sum(len(s) for s in _signals(P))
+    P.set_fused(0)
+    b = P.info()
+    assert b["fused"] == 0
+    red_f = b["bytes_fwd"] - b["bytes_fwd_kernel"]
+    red_b = b["bytes_bwd"] - b["bytes_bwd_kernel"]
+    assert a["bytes_fwd_kernel"] == b["bytes_fwd_kernel"] + red_f + 24 * n_sig == a["bytes_fwd"]
+    assert a["bytes_bwd_kernel"] == b["bytes_bwd_kernel"] + red_b + 24 * n_sig == a["bytes_bwd"]
+    P.set_fused(1)
+    assert P.info() == a
+    P.set_slot_layout(1)
+    assert P.info()["fused"] == 0
+    P.set_slot_layout(0)
+    assert P.info()["fused"] == 1
+    P.set_staging(0)
+    assert P.info()["fused"] == 0
+    P.set_staging(1)
+    assert P.info()["fused"] == 1
+    with pytest.raises(_lib.EpkError):
+        P.set_fused(2)
+    R = gen.rmat(scale=10, n_edges=6000, seed=5)
+    g = spmv_graph(R, R["shuffle"])
+    S = Plan(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"])
+    assert S.info()["fused"] == 0
+    with pytest.raises(_lib.EpkError) as e:
+        S.set_fused(1)
+    assert e.value.status == _lib.EPK_ESTATE
+    S.set_fused(0)
