@@ -237,6 +237,16 @@ void epk_plan_destroy(epk_plan *p);
  * state, output or (when the cost is nonzero) workspace, EPK_EHIP if a
  * launch fails.                                                           */
 int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream);
+/* epk_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results, bit for bit, with the replicated-vertex
+ * partials in a fixed 16 MiB array inside the library instead of d_ws.  No
+ * allocation of any kind.  The array is per device (held from module load
+ * until the process ends) and shared by every call on that device: calls
+ * that overlap on one device race.  stream must belong to the current
+ * device.  EPK_ERANGE if the plan's workspace_bytes exceed 16 MiB (tet55 at
+ * capacity 256 needs 8.8 MB); otherwise as epk_forward.                   */
+int epk_forward_scratch(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *stream);
 /* FLUX5 adjoint: g_q = (dr/dq)^T g_r on packed q, g_r, g_q (device
  * [n][5] float32), on the same partition, staging (Section 4) and reduction
  * as the forward: the upstream gradients are gathered per part like the

@@ -64,6 +64,7 @@ _SIGS = {
     "epk_plan_set_fused": (C.c_int, [_P, C.c_int32]),
     "epk_plan_destroy": (None, [_P]),
     "epk_forward": (C.c_int, [_P, _FP, _FP, C.c_float, _FP, _P, _P]),
+    "epk_forward_scratch": (C.c_int, [_P, _FP, _FP, C.c_float, _FP, _P]),
     "epk_backward": (C.c_int, [_P, _FP, _FP, _FP, _P, _P]),
     "epk_spmv": (C.c_int, [_P, _FP, _FP, _P, _P]),
     "epk_spmv_adjoint": (C.c_int, [_P, _FP, _FP, _FP, _FP, _P, _P]),

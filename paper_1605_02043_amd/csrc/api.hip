@@ -593,6 +593,49 @@ int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_
   return run_stage(p, EPK_OP_FORWARD, -1, q, nullptr, r, dt, q_new, d_ws, stream);
 }
 
+// ---- forward for callers that cannot allocate
+//
+// The replicated-vertex partials of epk_forward_scratch live in this fixed
+// array instead of a caller workspace.  Each device holds its own copy from
+// module load until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: the kernels get the address that
+// hipGetSymbolAddress returns with the device current (kept per device).
+// Nothing in the array has to start at zero: the part kernel writes every
+// partial before the reduction reads it.  Calls that overlap on one device
+// share the array and race.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::atomic<void *> g_scratch_ptr[kScratchDevices];
+
+static int scratch_of_current_device(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "current device");
+  if (dev < 0 || dev >= kScratchDevices) return fail(EPK_ERANGE, "device index beyond the scratch table");
+  void *ptr = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!ptr) {  // first call on this device: its copy's address (the same on every later call)
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e, "address of the scratch array");
+    if (!ptr) return fail(EPK_EHIP, "address of the scratch array is NULL");
+    g_scratch_ptr[dev].store(ptr, std::memory_order_release);
+  }
+  *out = ptr;
+  return EPK_OK;
+}
+
+int epk_forward_scratch(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *stream) {
+  clear_error();
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (p->kind != EPK_FLUX5) return fail(EPK_ESTATE, "op does not match the plan's kind");
+  if (p->ws_bytes > kScratchBytes) return fail(EPK_ERANGE, "the plan's partials exceed the 16 MiB scratch array");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  void *ws = nullptr;
+  const int st = scratch_of_current_device(&ws);
+  if (st) return st;
+  return run_stage(p, EPK_OP_FORWARD, -1, q, nullptr, r, dt, q_new, ws, stream);
+}
+
 int epk_backward(const epk_plan *p, const float *q, const float *g_r, float *g_q, void *d_ws, void *stream) {
   clear_error();
   return run_stage(p, EPK_OP_BACKWARD, -1, q, g_r, g_q, 0.f, nullptr, d_ws, stream);

@@ -431,6 +431,26 @@ def test_binding_checks_device_buffers():
             B.backward(good, good, out=b)
 
 
+def test_forward_scratch_refuses_large_workspace():
+    """epk_forward_scratch keeps the partials in a fixed 16 MiB array: a plan needing more is
+    refused (EPK_ERANGE) before anything touches a device; a plan that fits but was never
+    uploaded gets EPK_ESTATE."""
+    lib = _lib.lib
+    rng = np.random.default_rng(0)
+    n, m = 300_000, 600_000
+    u = rng.integers(0, n, m)
+    v = (u + 1 + rng.integers(0, n - 1, m)) % n
+    E = np.stack([u, v], 1).astype(np.int32)
+    P = Plan(E, n, 256, np.tile(np.float32([[1, 0, 0, 1]]), (m, 1)), order="input")
+    assert P.device_bytes()[1] > 16 << 20
+    assert lib.epk_forward_scratch(P._h, None, None, C.c_float(0.0), None, None) == _lib.EPK_ERANGE
+    assert b"16 MiB" in lib.epk_last_error()
+    Q = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
+    assert lib.epk_forward_scratch(Q._h, None, None, C.c_float(0.0), None, None) == _lib.EPK_ESTATE
+    S = Plan(np.array([[0, 2]]), 3, 4, np.ones(1, np.float32), kind="spmv", n_x=1)
+    assert lib.epk_forward_scratch(S._h, None, None, C.c_float(0.0), None, None) == _lib.EPK_ESTATE
+
+
 def _signals(P):
     """Signal records of the single-launch reduction, recounted from the plan's layout: each part
     signals the owner of every foreign vertex, and itself if a later part uses one of its vertices."""
