@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 GRAPH_TIMING = True  # cleared by --eager
 COLD_STEPS = 20  # set by --cold-steps
 REPLAYS = 20  # timed replays of the K-step graph for the spread
+SPMV_Y_WEIGHT = 4  # SpMV partition: a replicated y (partial, reduction) weighs 4 replicated x (one gather)
 CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
 
 
@@ -130,7 +131,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="tet55", choices=["tet55", "tet32", "rmat20", "batch256"])
+    ap.add_argument("--workload", default="tet55", choices=["tet55", "tet32", "tet80", "rmat20", "batch256"])
     ap.add_argument("--cap", type=int, default=256)
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0: the plan's default)")
     ap.add_argument("--swizzle", type=int, default=1, help="XCD-aware part mapping (1) or identity (0)")
@@ -708,11 +709,12 @@ def bench_spmv(args, torch):
     R = gen.rmat(20, 1 << 24, seed=0)
     m = len(R["rows"])
     res = {}
-    for name, perm_e, order in (("ep", R["shuffle"], "ep"), ("shuffled", R["shuffle"], "input"),
-                                ("row_sorted", np.argsort(R["rows"], kind="stable"), "input")):
+    for name, perm_e, order, cw in (("ep_weighted", R["shuffle"], "ep", (1, SPMV_Y_WEIGHT)),
+                                    ("ep", R["shuffle"], "ep", None), ("shuffled", R["shuffle"], "input", None),
+                                    ("row_sorted", np.argsort(R["rows"], kind="stable"), "input", None)):
         g = spmv_graph(R, perm_e)
         t0 = time.perf_counter()
-        P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"])
+        P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"], class_weight=cw)
         P.set_launch(args.wg, args.swizzle)
         P.upload("cuda")
         plan_s = time.perf_counter() - t0
@@ -792,12 +794,14 @@ def bench_spmv(args, torch):
                          plan_seconds=plan_s, partition_seconds=st["partition_seconds"])
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
         del P
-    ep = res["ep"]
+    ep = res["ep_weighted"]
     dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
     ach = ep["algorithmic_bytes"][dom] / (ep["kernels_ms"][dom] * 1e-3) / 1e9
     out = _common(args, "edges/s, SpMV y += A x, partitioned vs shuffled order, 1 MI355X", ep["edges_per_s"],
                   ep["ms_per_step"], {"workload": f"rmat20: R-MAT 2^20 x 2^20, {m} nonzeros (a,b,c)=(0.57,0.19,0.19), "
-                                                  f"w~U[0,1), x~N(0,1), capacity {args.cap}, partitioned order",
+                                                  f"w~U[0,1), x~N(0,1), capacity {args.cap}, partitioned order "
+                                                  f"(EP with y copies weighing {SPMV_Y_WEIGHT}; the uniform-weight EP "
+                                                  f"order is under orders.ep)",
                                       "capacity": args.cap,
                                       "timing": ("step: the timed steps captured in one HIP graph, one replay; "
                                                  "kernels: HIP events in eager steps") if GRAPH_TIMING

@@ -31,6 +31,8 @@ WORKLOADS = {
     "rmat20": dict(kind="spmv", builder="rmat", args=(20, 1 << 24), cap=256),
     "batch256": dict(kind="batch", builder="batch_graphs", args=(256,), cap=None),
     "tet55": dict(kind="flux", builder="tet_mesh", args=(55, 55, 55), cap=256),
+    # a mesh whose step working set (~0.45 GB) exceeds the 256 MiB MALL: back-to-back steps stream HBM
+    "tet80": dict(kind="flux", builder="tet_mesh", args=(80, 80, 80), cap=256),
 }
 
 

@@ -117,10 +117,26 @@ typedef struct epk_batch epk_batch;
  * Host only, synchronous; geometry is not read.                          */
 int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *part_of_edge,
                   int32_t *task_order, epk_stats *stats);
+/* The same with per-class vertex weights, EP order only: the partition
+ * minimises sum_v w(v) (p_v - 1), Definition 2's cost with each replicated
+ * copy of a vertex weighted by its class, through the same transform
+ * (Section 3.2) with every chain link of vertex v weighing w(v).
+ * class_weight[2] = {x, y}: x are vertices below n_x, y the rest (FLUX5
+ * graphs have n_x = 0, so class_weight[1] applies to all).  {1, 1} (or
+ * NULL) is the paper's uniform cost.  For SpMV a replicated y costs a
+ * partial write, a read and a reduction step where a replicated x costs one
+ * 4-byte gather, so {1, 4} trades x copies for y copies.  Weights 1..64;
+ * EPK_EINVAL for other orders with weights other than {1, 1}.  stats
+ * report the unweighted cost.                                             */
+int epk_partition_weighted(const epk_graph *g, int32_t capacity, int32_t order, const int32_t *class_weight,
+                           int32_t *part_of_edge, int32_t *task_order, epk_stats *stats);
 
 /* Plan = partition + data packing along the task order (Section 4.1) + the
  * device image the kernels read.  Host only, synchronous.                */
 int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind, epk_plan **out);
+/* epk_plan_create with per-class vertex weights (see epk_partition_weighted). */
+int epk_plan_create_weighted(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind,
+                             const int32_t *class_weight, epk_plan **out);
 /* The same plan from a partition the caller made (Definition 2's output,
  * e.g. from an offline partitioner): part_of_edge[m] in [0, n_parts);
  * task_order[m] lists the edges part by part, parts ascending (NULL:

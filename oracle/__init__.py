@@ -49,12 +49,13 @@ independent implementations agreeing bit for bit.
 from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines  # noqa: F401
 
 
-def partition(edges, n, cap, order="ep"):
+def partition(edges, n, cap, order="ep", class_weight=None, n_x=0):
     """(part, task_order) for an order: 'ep' (multilevel, the default), 'ggp'
     (single-pass greedy growing), 'input' (consecutive blocks), or the
-    baselines 'random' and 'greedy'."""
+    baselines 'random' and 'greedy'.  class_weight (EP only): per-class vertex
+    weights (x: ids below n_x, y: the rest)."""
     if order == "ep":
-        part, task, _ = multilevel.partition(edges, n, cap)
+        part, task, _ = multilevel.partition(edges, n, cap, class_weight, n_x)
         return part, task
     if order == "ggp":
         return ggp.partition(edges, n, cap, order="ep")

@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-from .cost import partition_cost
+from .cost import partition_cost, weighted_cost
 from .graph import clone_and_connect, vertex_cut
 
 
@@ -38,13 +38,14 @@ def restricted_growth(m: int, max_blocks: int, cap: int):
     yield from rec(0, 0)
 
 
-def min_edge_partition_cost(edges, n: int, cap: int):
-    """Minimum C over all capacity-feasible edge partitions, and one minimiser."""
+def min_edge_partition_cost(edges, n: int, cap: int, w=None):
+    """Minimum C (or, with vertex weights w, sum_v w[v] (p_v - 1)) over all capacity-feasible
+    edge partitions, and one minimiser."""
     m = len(edges)
     k = math.ceil(m / cap)
     best, arg = None, None
     for a in restricted_growth(m, k, cap):
-        c = partition_cost(edges, n, a, k)["cost"]
+        c = partition_cost(edges, n, a, k)["cost"] if w is None else weighted_cost(edges, n, a, w)
         if best is None or c < best:
             best, arg = c, a
     return best, np.asarray(arg)

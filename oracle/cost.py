@@ -77,3 +77,30 @@ def loads_simple(edges, part) -> int:
     for (u, v), p in zip(np.asarray(edges).tolist(), np.asarray(part).tolist()):
         groups.setdefault(p, set()).update((u, v))
     return sum(len(s) for s in groups.values())
+
+
+def weighted_cost(edges: np.ndarray, n: int, part, w) -> int:
+    """Definition 2's cost with vertex weights: sum over active v of w[v] (p_v - 1).
+    w[v] = 1 for every v is C itself."""
+    p_v = partition_cost(edges, n, part)["p_v"]
+    w = np.asarray(w, dtype=np.int64)
+    active = p_v >= 1
+    return int((w[active] * (p_v[active] - 1)).sum())
+
+
+def weighted_aux_cut(edges: np.ndarray, part, w) -> int:
+    """Cut auxiliary edges of the index-order transform, each weighing w of the vertex whose
+    chain it links (Theorem 1 with weights: weighted_cost <= weighted_aux_cut)."""
+    edges = np.asarray(edges, dtype=np.int64)
+    part = np.asarray(part, dtype=np.int64)
+    w = np.asarray(w, dtype=np.int64)
+    m = len(edges)
+    if m == 0:
+        return 0
+    vert = np.concatenate([edges[:, 0], edges[:, 1]])
+    eid = np.concatenate([np.arange(m), np.arange(m)])
+    srt = np.lexsort((eid, vert))
+    vert, eid = vert[srt], eid[srt]
+    link = vert[1:] == vert[:-1]
+    a, b, v = eid[:-1][link], eid[1:][link], vert[:-1][link]
+    return int((w[v] * (part[a] != part[b])).sum())

@@ -8,7 +8,11 @@ partition the coarsest graph, project back and refine the boundary), applied
 to D' with original edges contracted (infinite weight, so never cut):
 
 * node = an edge of the data-affinity graph, weight 1;
-* link weight = number of auxiliary edges of D' between two contracted nodes.
+* link weight = number of auxiliary edges of D' between two contracted nodes
+  (with per-class vertex weights, the sum of the weights of the vertices whose
+  chains those auxiliary edges link: the cost becomes sum_v w(v) (p_v - 1),
+  Definition 2 with weighted copies, and Theorem 1 holds for it with the
+  weighted cut).
 
 Capacity reading: a hard maximum of c edges per part with 5% room,
 k = ceil(m / (c - floor(c/20))) parts, growth target T = ceil(m / k), so the
@@ -62,13 +66,26 @@ def parameters(m: int, cap: int):
     return k, math.ceil(m / k), max_node_weight(cap)
 
 
-def _finest(edges, n):
+def _finest(edges, n, class_weight=None, n_x=0):
+    """Contracted D': node e per edge, a link weight per pair of nodes.  Each auxiliary edge
+    (consecutive edges of vertex v's incidence list) adds the weight of v's class (x: v < n_x,
+    y: the rest) to its link, 1 without class weights."""
     m = len(edges)
-    nbr = contracted_links(edges, n, incidence(edges, n))
     adj = [dict() for _ in range(m)]
-    for e in range(m):
-        for f in nbr[e]:
-            adj[e][f] = adj[e].get(f, 0) + 1
+    if class_weight is None:
+        nbr = contracted_links(edges, n, incidence(edges, n))
+        for e in range(m):
+            for f in nbr[e]:
+                adj[e][f] = adj[e].get(f, 0) + 1
+        return adj, [1] * m
+    inc = incidence(edges, n)
+    for v in range(n):
+        w = class_weight[0] if v < n_x else class_weight[1]
+        chain = inc[v]
+        for t in range(len(chain) - 1):
+            a, b = chain[t], chain[t + 1]
+            adj[a][b] = adj[a].get(b, 0) + w
+            adj[b][a] = adj[b].get(a, 0) + w
     return adj, [1] * m
 
 
@@ -246,8 +263,9 @@ def contiguity(adj, w, part, k, cap):
     return part
 
 
-def partition(edges: np.ndarray, n: int, cap: int):
-    """Return (part[m], task_order[m], k) as int64 arrays / int."""
+def partition(edges: np.ndarray, n: int, cap: int, class_weight=None, n_x: int = 0):
+    """Return (part[m], task_order[m], k) as int64 arrays / int.  class_weight = (x, y):
+    per-class vertex weights of the weighted cost sum_v w(v) (p_v - 1), x being v < n_x."""
     edges = np.asarray(edges, dtype=np.int64)
     m = len(edges)
     if cap < 1:
@@ -255,7 +273,7 @@ def partition(edges: np.ndarray, n: int, cap: int):
     k, target, maxw = parameters(m, cap)
     if m == 0:
         return np.zeros(0, np.int64), np.zeros(0, np.int64), 0
-    adj, w = _finest(edges, n)
+    adj, w = _finest(edges, n, class_weight, n_x)
     levels = []
     while len(adj) > 16 * k:
         cadj, cw, cmap = coarsen(adj, w, maxw)

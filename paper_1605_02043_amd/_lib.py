@@ -47,7 +47,10 @@ _SZP = C.POINTER(C.c_size_t)
 
 _SIGS = {
     "epk_partition": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, _I32P, _I32P, C.POINTER(Stats)]),
+    "epk_partition_weighted": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, _I32P, _I32P, _I32P,
+                                         C.POINTER(Stats)]),
     "epk_plan_create": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "epk_plan_create_weighted": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
     "epk_plan_create_partitioned": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int64, _I32P, _I32P, C.c_int32,
                                               C.POINTER(_P)]),
     "epk_plan_device_bytes": (C.c_int, [_P, _SZP, _SZP]),

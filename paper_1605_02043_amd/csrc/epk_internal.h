@@ -38,7 +38,11 @@ struct Incidence {
 int validate_graph(const epk_graph *g, int32_t kind_or_minus1);
 void build_incidence(int32_t n, int64_t m, const int32_t *uv, Incidence &inc);
 // nbr[4e .. 4e+3]: predecessor/successor of e in inc[u_e] and inc[v_e], -1 if absent.
-void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr);
+// nbw (optional): the weight of each link slot, the class weight of the chain's vertex (x: id below
+// n_x, y: the rest; class_weight NULL: 1)
+void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr,
+                      std::vector<int32_t> *nbw = nullptr, int32_t n_x = 0, const int32_t *class_weight = nullptr);
+constexpr int32_t kMaxClassWeight = 64;
 void greedy_growing(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
                     std::vector<int32_t> &task);
 void input_order(int64_t m, int32_t cap, std::vector<int32_t> &part, std::vector<int32_t> &task);
@@ -51,12 +55,13 @@ void greedy_vertex_cut(int32_t n, int64_t m, const int32_t *uv, int32_t cap, std
 struct CapacityExceeded {};
 int64_t multilevel_parts(int64_t m, int32_t cap);
 int32_t multilevel_max_node_weight(int32_t cap);
-void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
-                std::vector<int32_t> &task);
+void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, const std::vector<int32_t> *nbw,
+                std::vector<int32_t> &part, std::vector<int32_t> &task);
 void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const std::vector<int32_t> &part,
                      const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st);
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
-                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out);
+                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out,
+                  const int32_t *class_weight = nullptr);
 // A caller's partition: part_in[m] in [0, k); task_in[m] (may be NULL: parts
 // ascending, edge id inside a part) a permutation listing parts in order.
 // Capacity is not checked here (plan_build refuses parts above it).
@@ -201,7 +206,8 @@ inline bool fused_in_use(const epk_plan *p) {
 // order < 0: the partition comes from the caller (given_k parts, given_part,
 // given_task as for given_partition).
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status,
-                     int64_t given_k = 0, const int32_t *given_part = nullptr, const int32_t *given_task = nullptr);
+                     int64_t given_k = 0, const int32_t *given_part = nullptr, const int32_t *given_task = nullptr,
+                     const int32_t *class_weight = nullptr);
 // Reduction records, one per replicated vertex: its packed id and its (at
 // most kRecSlots) slots, -1 past the last; a first slot of -1 sends the
 // vertex to the slot lists (more slots than a record holds).

@@ -39,25 +39,29 @@ struct LGraph {
   std::vector<int32_t> w;    // node weights
 };
 
-// Finest level from the contracted links (4 slots per node, -1 if absent).
-LGraph finest(int64_t m, const std::vector<int32_t> &nbr) {
+// Finest level from the contracted links (4 slots per node, -1 if absent); a link's weight is the
+// number of chain links between its two nodes, or the sum of their slot weights nbw.
+LGraph finest(int64_t m, const std::vector<int32_t> &nbr, const std::vector<int32_t> *nbw) {
   LGraph G;
   G.n = int32_t(m);
   G.off.assign(size_t(m) + 1, 0);
   G.w.assign(size_t(m), 1);
   G.nb.reserve(size_t(4 * m));
   G.lw.reserve(size_t(4 * m));
-  int32_t tmp[4];
+  int64_t tmp[4];  // neighbour << 32 | slot weight, sorted by neighbour
   for (int64_t e = 0; e < m; ++e) {
     int c = 0;
-    for (int j = 0; j < 4; ++j)
-      if (nbr[4 * size_t(e) + j] >= 0) tmp[c++] = nbr[4 * size_t(e) + j];
+    for (int j = 0; j < 4; ++j) {
+      const int32_t x = nbr[4 * size_t(e) + j];
+      if (x >= 0) tmp[c++] = (int64_t(x) << 32) | (nbw ? (*nbw)[4 * size_t(e) + j] : 1);
+    }
     std::sort(tmp, tmp + c);
     for (int j = 0; j < c;) {
       int r = j;
-      while (r < c && tmp[r] == tmp[j]) ++r;
-      G.nb.push_back(tmp[j]);
-      G.lw.push_back(r - j);
+      int32_t w = 0;
+      while (r < c && (tmp[r] >> 32) == (tmp[j] >> 32)) w += int32_t(tmp[r++] & 0xffffffff);
+      G.nb.push_back(int32_t(tmp[j] >> 32));
+      G.lw.push_back(w);
       j = r;
     }
     G.off[e + 1] = int64_t(G.nb.size());
@@ -345,8 +349,8 @@ int64_t multilevel_parts(int64_t m, int32_t cap) {
   return (m + t0 - 1) / t0;
 }
 
-void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::vector<int32_t> &part,
-                std::vector<int32_t> &task) {
+void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, const std::vector<int32_t> *nbw,
+                std::vector<int32_t> &part, std::vector<int32_t> &task) {
   part.assign(size_t(m), 0);
   task.resize(size_t(m));
   if (m == 0) return;
@@ -355,7 +359,7 @@ void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, std::ve
   const int32_t maxw = multilevel_max_node_weight(cap);
   std::vector<LGraph> levels;
   std::vector<std::vector<int32_t>> cmaps;
-  levels.push_back(finest(m, nbr));
+  levels.push_back(finest(m, nbr, nbw));
   while (int64_t(levels.back().n) > 16 * int64_t(k)) {
     check_cancel();
     std::vector<int32_t> cmap;

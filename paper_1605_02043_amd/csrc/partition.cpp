@@ -75,14 +75,22 @@ void build_incidence(int32_t n, int64_t m, const int32_t *uv, Incidence &inc) {
   }
 }
 
-void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr) {
+void contracted_links(int64_t m, const int32_t *uv, const Incidence &inc, std::vector<int32_t> &nbr,
+                      std::vector<int32_t> *nbw, int32_t n_x, const int32_t *class_weight) {
   nbr.assign(size_t(4 * m), -1);
-  // fill count per node; each chain link (a, b) adds b to a's list and a to b's
+  if (nbw) nbw->assign(size_t(4 * m), 0);
+  // fill count per node; each chain link (a, b) adds b to a's list and a to b's, with the weight
+  // of the chain's vertex class (x: vertices below n_x, y: the rest)
   std::vector<uint8_t> cnt(size_t(m), 0);
   const int64_t n = int64_t(inc.off.size()) - 1;
   for (int64_t v = 0; v < n; ++v) {
+    const int32_t w = class_weight ? class_weight[v < n_x ? 0 : 1] : 1;
     for (int64_t t = inc.off[v]; t + 1 < inc.off[v + 1]; ++t) {
       const int32_t a = inc.adj[t], b = inc.adj[t + 1];
+      if (nbw) {
+        (*nbw)[4 * size_t(a) + cnt[a]] = w;
+        (*nbw)[4 * size_t(b) + cnt[b]] = w;
+      }
       nbr[4 * size_t(a) + cnt[a]++] = b;
       nbr[4 * size_t(b) + cnt[b]++] = a;
     }
@@ -212,9 +220,16 @@ void check_cancel() {
 }
 
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
-                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out) {
+                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out, const int32_t *class_weight) {
   if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
   if (order < EPK_ORDER_EP || order > EPK_ORDER_GREEDY) return fail(EPK_EINVAL, "unknown order");
+  if (class_weight) {
+    for (int c = 0; c < 2; ++c)
+      if (class_weight[c] < 1 || class_weight[c] > kMaxClassWeight)
+        return fail(EPK_EINVAL, "class weights must be 1..64");
+    if (order != EPK_ORDER_EP && (class_weight[0] != 1 || class_weight[1] != 1))
+      return fail(EPK_EINVAL, "class weights apply to the EP order only");
+  }
   std::memset(&st, 0, sizeof(st));
   try {
     const auto t0 = std::chrono::steady_clock::now();
@@ -229,13 +244,14 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
     } else if (order == EPK_ORDER_GREEDY) {
       greedy_vertex_cut(g->n_vertices, m, g->edge_uv, cap, part, task);
     } else {
-      std::vector<int32_t> nbr;
-      contracted_links(m, g->edge_uv, inc, nbr);
+      std::vector<int32_t> nbr, nbw;
+      const bool weighted = class_weight && (class_weight[0] != 1 || class_weight[1] != 1);
+      contracted_links(m, g->edge_uv, inc, nbr, weighted ? &nbw : nullptr, g->n_x, class_weight);
       if (order == EPK_ORDER_GGP) {
         greedy_growing(m, cap, nbr, part, task);
       } else {
         k = multilevel_parts(m, cap);
-        multilevel(m, cap, nbr, part, task);
+        multilevel(m, cap, nbr, weighted ? &nbw : nullptr, part, task);
       }
     }
     const auto t1 = std::chrono::steady_clock::now();
@@ -300,13 +316,18 @@ extern "C" {
 
 int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *part_of_edge,
                   int32_t *task_order, epk_stats *stats) {
+  return epk_partition_weighted(g, capacity, order, nullptr, part_of_edge, task_order, stats);
+}
+
+int epk_partition_weighted(const epk_graph *g, int32_t capacity, int32_t order, const int32_t *class_weight,
+                           int32_t *part_of_edge, int32_t *task_order, epk_stats *stats) {
   epk::clear_error();
   int s = epk::validate_graph(g, -1);
   if (s) return s;
   if (g->n_edges > 0 && !part_of_edge) return epk::fail(EPK_EINVAL, "part_of_edge is NULL");
   std::vector<int32_t> part, task;
   epk_stats st;
-  s = epk::run_partition(g, capacity, order, part, task, st, nullptr);
+  s = epk::run_partition(g, capacity, order, part, task, st, nullptr, class_weight);
   if (s) return s;
   if (g->n_edges > 0) {
     std::memcpy(part_of_edge, part.data(), sizeof(int32_t) * size_t(g->n_edges));

@@ -31,14 +31,26 @@ def make_graph(edges: np.ndarray, n: int, geom: np.ndarray | None = None, n_x: i
     return gs, (edges, geom, g)
 
 
-def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep"):
-    """Edge partition (host): returns (part[m], task_order[m], stats dict)."""
-    gs, keep = make_graph(edges, n)
+def _class_weight(class_weight):
+    if class_weight is None:
+        return None
+    w = np.ascontiguousarray(class_weight, dtype=np.int32)
+    if w.shape != (2,):
+        raise ValueError("class_weight must be two integers (x class, y class)")
+    return w
+
+
+def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep", class_weight=None, n_x: int = 0):
+    """Edge partition (host): returns (part[m], task_order[m], stats dict).  class_weight
+    (EP order): per-class vertex weights {x, y}, x being the vertices below n_x."""
+    gs, keep = make_graph(edges, n, None, n_x)
     m = gs.n_edges
     part = np.empty(m, dtype=np.int32)
     task = np.empty(m, dtype=np.int32)
     st = Stats()
-    check(lib.epk_partition(C.byref(gs), int(cap), _lib.ORDER[order], i32p(part), i32p(task), C.byref(st)))
+    w = _class_weight(class_weight)
+    check(lib.epk_partition_weighted(C.byref(gs), int(cap), _lib.ORDER[order], i32p(w), i32p(part), i32p(task),
+                                     C.byref(st)))
     del keep
     return part, task, st.as_dict()
 
@@ -83,15 +95,19 @@ class Plan:
     States handed to the device calls are in PACKED vertex order.
     """
 
-    def __init__(self, edges, n: int, cap: int, geom, order: str = "ep", kind: str = "flux5", n_x: int = 0):
+    def __init__(self, edges, n: int, cap: int, geom, order: str = "ep", kind: str = "flux5", n_x: int = 0,
+                 class_weight=None):
         self.kind = kind
         self.n = int(n)
         self.n_x = int(n_x)
         self.m = int(len(edges))
         self.cap = int(cap)
+        self._h = None
         gs, keep = make_graph(edges, n, geom, n_x)
         h = C.c_void_p()
-        check(lib.epk_plan_create(C.byref(gs), int(cap), _lib.ORDER[order], _lib.KIND[kind], C.byref(h)))
+        w = _class_weight(class_weight)
+        check(lib.epk_plan_create_weighted(C.byref(gs), int(cap), _lib.ORDER[order], _lib.KIND[kind], i32p(w),
+                                           C.byref(h)))
         del keep
         self._h = h
         self.image = None

@@ -507,3 +507,41 @@ def test_single_launch_reduction_accounting_and_switch():
         S.set_fused(1)
     assert e.value.status == _lib.EPK_ESTATE
     S.set_fused(0)
+
+
+def test_weighted_partition_parity_and_errors():
+    """The library's weighted EP partition equals the oracle's bit for bit (random bipartite
+    graphs, several weights; the hand-derived K2,2 case), {1, 1} equals the unweighted call, and
+    bad weights or weights on other orders are refused."""
+    from oracle import multilevel
+
+    K22 = np.array([[0, 2], [0, 3], [1, 2], [1, 3]], dtype=np.int32)
+    part, task, _ = partition(K22, 4, 2, "ep", class_weight=(1, 4), n_x=2)
+    assert part.tolist() == [0, 1, 0, 1] and task.tolist() == [0, 2, 1, 3]
+    rng = np.random.default_rng(77)
+    for trial in range(30):
+        n_x, n_y = int(rng.integers(2, 60)), int(rng.integers(2, 60))
+        m = int(rng.integers(1, 700))
+        cap = int(rng.integers(1, 48))
+        wx, wy = int(rng.integers(1, 5)), int(rng.integers(1, 9))
+        E = np.stack([rng.integers(0, n_x, m), n_x + rng.integers(0, n_y, m)], 1).astype(np.int32)
+        p1, t1, st1 = partition(E, n_x + n_y, cap, "ep", class_weight=(wx, wy), n_x=n_x)
+        p2, t2, _ = multilevel.partition(E, n_x + n_y, cap, class_weight=(wx, wy), n_x=n_x)
+        assert np.array_equal(p1, p2) and np.array_equal(t1, t2), (trial, wx, wy)
+        assert st1["max_part_edges"] <= cap
+    pu, tu, _ = partition(E, n_x + n_y, cap, "ep")
+    pw, tw, _ = partition(E, n_x + n_y, cap, "ep", class_weight=(1, 1), n_x=n_x)
+    assert np.array_equal(pu, pw) and np.array_equal(tu, tw)
+    for bad in ((0, 1), (1, 65)):
+        with pytest.raises(_lib.EpkError) as e:
+            partition(E, n_x + n_y, cap, "ep", class_weight=bad, n_x=n_x)
+        assert e.value.status == _lib.EPK_EINVAL
+    with pytest.raises(_lib.EpkError) as e:
+        partition(E, n_x + n_y, cap, "ggp", class_weight=(1, 4), n_x=n_x)
+    assert e.value.status == _lib.EPK_EINVAL
+    partition(E, n_x + n_y, cap, "input", class_weight=(1, 1), n_x=n_x)
+    g = spmv_graph(gen.rmat(scale=9, n_edges=3000, seed=4), np.arange(3000))
+    P = Plan(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"], class_weight=(1, 4))
+    p3, t3 = P.part_of_edge()
+    p4, t4 = multilevel.partition(g["edges"], g["n"], 128, class_weight=(1, 4), n_x=g["n_x"])[:2]
+    assert np.array_equal(p3, p4) and np.array_equal(t3, t4)

@@ -18,10 +18,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run(g, cap, order, x):
+def _run(g, cap, order, x, class_weight=None):
     from paper_1605_02043_amd import Plan
 
-    P = Plan(g["edges"], g["n"], cap, g["w"], order=order, kind="spmv", n_x=g["n_x"]).upload("cuda")
+    P = Plan(g["edges"], g["n"], cap, g["w"], order=order, kind="spmv", n_x=g["n_x"],
+             class_weight=class_weight).upload("cuda")
     perm = P.perm()
     n_x = g["n_x"]
     xp = torch.from_numpy(np.ascontiguousarray(x[perm[:n_x]])).cuda()
@@ -43,6 +44,30 @@ def test_spmv_rmat_small(order, cap):
     ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
     A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
     assert_close(f"spmv14/{order}/{cap}", y, ref, A)
+
+
+@pytest.mark.parametrize("cap", [256, 1024])
+def test_spmv_rmat_weighted_partition(cap):
+    """EP with y copies weighing 4 (the partition cuts x chains before y chains): the same
+    kernels on a plan with few replicated y, forward and adjoint against the oracle."""
+    R = gen.rmat(scale=14, n_edges=1 << 18, seed=2)
+    g = spmv_graph(R, R["shuffle"])
+    say(f"case spmv scale14 weighted cap={cap}")
+    y, P = _run(g, cap, "ep", R["x"], class_weight=(1, 4))
+    ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    assert_close(f"spmv14/weighted/{cap}", y, ref, A)
+    perm = P.perm()
+    n_x = g["n_x"]
+    gy = np.random.default_rng(3).standard_normal(g["n"] - n_x).astype(np.float32)
+    gyp = torch.from_numpy(np.ascontiguousarray(gy[perm[n_x:] - n_x])).cuda()
+    gx = P.spmv_adjoint(gyp)
+    torch.cuda.synchronize()
+    out = np.empty(n_x, dtype=np.float32)
+    out[perm[:n_x]] = gx.cpu().numpy()
+    gref = spmv.backward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)[0]
+    gA = spmv.backward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)[0]
+    assert_close(f"spmv14/weighted/{cap}/adjoint", out, gref, gA)
 
 
 def test_spmv_rmat_full_size_three_orders():

@@ -587,3 +587,67 @@ def test_baselines_rank_below_ep_on_a_mesh():
         part, _ = oracle.partition(G["edges"], G["n"], 64, order)
         k[order] = cost.partition_cost(G["edges"], G["n"], part, int(part.max()) + 1)["cost"]
     assert k["ep"] < k["greedy"] < k["random"]
+
+
+# ---------------------------------------------------------------- per-class vertex weights
+
+# A hand-derived case: x vertices 0, 1 and y vertices 2, 3 (n_x = 2), edges
+# e0 = (x0, y0), e1 = (x0, y1), e2 = (x1, y0), e3 = (x1, y1), capacity 2 (k = 2, no coarsening).
+# Chains: x0 links e0-e1, x1 links e2-e3, y0 links e0-e2, y1 links e1-e3.
+# Uniform weights: growth starts at e0, whose links to e1 (x0) and e2 (y0) tie at 1, so the
+#   smaller id e1 joins: parts {e0, e1} | {e2, e3}; both y vertices are replicated (C = 2).
+# Weights (x 1, y 4): e2's link weighs 4, so e2 joins: parts {e0, e2} | {e1, e3}; both x vertices
+#   are replicated, weighted cost 1 + 1 = 2 (the uniform split would cost 4 + 4 = 8).
+_K22 = np.array([[0, 2], [0, 3], [1, 2], [1, 3]])
+
+
+def test_weighted_multilevel_hand_derived():
+    part, task, k = multilevel.partition(_K22, 4, 2)
+    assert part.tolist() == [0, 0, 1, 1] and task.tolist() == [0, 1, 2, 3]
+    part_w, task_w, _ = multilevel.partition(_K22, 4, 2, class_weight=(1, 4), n_x=2)
+    assert part_w.tolist() == [0, 1, 0, 1] and task_w.tolist() == [0, 2, 1, 3]
+    w = np.array([1, 1, 4, 4])
+    assert cost.weighted_cost(_K22, 4, part, w) == 8 and cost.weighted_cost(_K22, 4, part_w, w) == 2
+    best, _ = brute.min_edge_partition_cost(_K22, 4, 2, w)
+    assert best == 2
+    # uniform weights (1, 1) are the paper's cost: the same partition as no weights
+    p1, t1, _ = multilevel.partition(_K22, 4, 2, class_weight=(1, 1), n_x=2)
+    assert p1.tolist() == part.tolist() and t1.tolist() == task.tolist()
+
+
+def test_weighted_cost_definitions():
+    """weighted_cost with unit weights is C; weighted_aux_cut with unit weights is the aux cut."""
+    rng = np.random.default_rng(5)
+    E = _random_graph(rng, 12, 40)
+    part = rng.integers(0, 5, 40)
+    c = cost.partition_cost(E, 12, part)
+    assert cost.weighted_cost(E, 12, part, np.ones(12)) == c["cost"]
+    assert cost.weighted_aux_cut(E, part, np.ones(12)) == c["aux_cut"]
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(2, 15), st.integers(2, 15), st.integers(1, 120), st.integers(1, 30), st.integers(1, 8),
+       st.integers(0, 10_000))
+def test_weighted_multilevel_invariants_and_theorem1(n_x, n_y, m, cap, wy, seed):
+    """Weighted EP on random bipartite graphs: every edge once within the capacity, and the
+    weighted form of Theorem 1: sum_v w(v) (p_v - 1) <= the weighted cut of the transform."""
+    rng = np.random.default_rng(seed)
+    E = np.stack([rng.integers(0, n_x, m), n_x + rng.integers(0, n_y, m)], 1)
+    part, task, k = multilevel.partition(E, n_x + n_y, cap, class_weight=(1, wy), n_x=n_x)
+    assert sorted(task.tolist()) == list(range(m))
+    assert np.bincount(part, minlength=k).max() <= cap
+    w = np.array([1] * n_x + [wy] * n_y)
+    assert cost.weighted_cost(E, n_x + n_y, part, w) <= cost.weighted_aux_cut(E, part, w)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_multilevel_not_below_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    n_x, n_y = int(rng.integers(2, 4)), int(rng.integers(2, 4))
+    m = int(rng.integers(3, 8))
+    cap = int(rng.integers(2, 4))
+    E = np.stack([rng.integers(0, n_x, m), n_x + rng.integers(0, n_y, m)], 1)
+    w = np.array([1] * n_x + [5] * n_y)
+    part, _, k = multilevel.partition(E, n_x + n_y, cap, class_weight=(1, 5), n_x=n_x)
+    best, _ = brute.min_edge_partition_cost(E, n_x + n_y, cap, w)
+    assert cost.weighted_cost(E, n_x + n_y, part, w) >= best
