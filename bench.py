@@ -48,8 +48,8 @@ def source_sha256() -> str:
 
 
 def measured_traffic(workload: str):
-    """Per-launch HBM bytes (FETCH_SIZE, WRITE_SIZE, scaled by the copy calibration)
-    from the committed counter summary, or None if it belongs to other sources."""
+    """Per-launch L2-miss traffic (request-size counters) from the committed counter summary,
+    or None if it belongs to other sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -126,6 +126,88 @@ def summarize_counters(paths) -> str:
     return "\n".join(out)
 
 
+def _counter_table(paths):
+    """{(short kernel name, workgroups): {counter: mean value per dispatch}} from rocprofv3 CSVs."""
+    import csv
+
+    acc = {}
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                wg = max(int(r["Workgroup_Size"]), 1)
+                key = (_short_name(r["Kernel_Name"]), int(r["Grid_Size"]) // wg)
+                acc.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: float(np.mean(v)) for c, v in d.items()} for k, d in acc.items()}
+
+
+def _bytes_of(c):
+    """L2-miss traffic of one dispatch from the request counters (TCC_EA0_*, summed over the
+    device): reads by request size, 32 / 64 / 128 bytes, writes as 32 or 64 bytes; also the
+    rocprofv3 FETCH_SIZE expression (which takes TCC_BUBBLE as the count of 128-byte reads)."""
+    out = {}
+    if "TCC_EA0_RDREQ_sum" in c:
+        r32, r64, r128 = (c.get(f"TCC_EA0_RDREQ_{b}B_sum", 0.0) for b in (32, 64, 128))
+        other = max(c["TCC_EA0_RDREQ_sum"] - r32 - r64 - r128, 0.0)
+        out["read_bytes"] = 32 * r32 + 64 * r64 + 128 * r128 + 64 * other
+        out["read_requests"] = {"32B": r32, "64B": r64, "128B": r128, "other": other}
+    if "TCC_EA0_WRREQ_sum" in c:
+        w64 = c.get("TCC_EA0_WRREQ_64B_sum", 0.0)
+        out["write_bytes"] = 32 * (c["TCC_EA0_WRREQ_sum"] - w64) + 64 * w64
+    if "TCC_BUBBLE_sum" in c and "read_requests" in out:
+        rq = out["read_requests"]
+        tot = rq["32B"] + rq["64B"] + rq["128B"] + rq["other"]
+        out["fetch_size_expression_bytes"] = (128 * c["TCC_BUBBLE_sum"] + 64 * (tot - c["TCC_BUBBLE_sum"] - rq["32B"])
+                                              + 32 * rq["32B"])
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        out["l2_hit_rate"] = c["TCC_HIT_sum"] / max(c["TCC_HIT_sum"] + c["TCC_MISS_sum"], 1.0)
+    return out
+
+
+def traffic_json(workload: str, paths, cap: int = 256) -> dict:
+    """Per-launch L2-miss traffic (reads to the fabric, MALL hits included, and writes) of the
+    partitioned and default-order kernels of a mesh workload, from counter CSVs of
+    `bench.py --eager ...` runs; dispatches are told apart by their grid (plans rebuilt here)."""
+    import gen
+    from paper_1605_02043_amd import Plan
+
+    G = gen.workload(workload, seed=0)
+    m = len(G["edges"])
+    table = _counter_table(paths)
+    out = {"source_sha256": source_sha256(), "workload": workload,
+           "counters": "TCC_EA0_RDREQ{,_32B,_64B,_128B}_sum, TCC_EA0_WRREQ{,_64B}_sum, TCC_BUBBLE_sum, "
+                       "TCC_HIT_sum, TCC_MISS_sum per dispatch (rocprofv3 --pmc, three passes); bytes = L2 misses to "
+                       "the fabric by request size (MALL hits included) plus writes"}
+    for order in ("ep", "input"):
+        P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order)
+        info, st = P.info(), P.stats
+        k = info["n_parts"]
+        grid_part = 8 * ((k + 7) // 8)
+        grid_red = (st["replicated"] + (G["n"] - st["n_active"]) + 255) // 256
+        algo = {"flux_fwd": info["bytes_fwd_kernel"], "flux_bwd": info["bytes_bwd_kernel"],
+                "reduce_fwd": info["bytes_fwd"] - info["bytes_fwd_kernel"],
+                "reduce_bwd": info["bytes_bwd"] - info["bytes_bwd_kernel"]}
+        res = {}
+        for (name, nwg), c in table.items():
+            if name.startswith("flux_fwd_kernel") and nwg == grid_part:
+                stage = "flux_fwd"
+            elif name.startswith("flux_bwd_kernel") and nwg == grid_part:
+                stage = "flux_bwd"
+            elif name.startswith("reduce_kernel") and nwg == grid_red:
+                stage = "reduce"
+            else:
+                continue
+            b = _bytes_of(c)
+            for st_name in ((stage,) if stage != "reduce" else ("reduce_fwd", "reduce_bwd")):
+                e = res.setdefault(st_name, {"kernel": name, "workgroups": nwg, "launches_per_step": 1})
+                e.update(b)
+                e["bytes"] = e.get("read_bytes", 0.0) + e.get("write_bytes", 0.0)
+                e["algorithmic_bytes"] = algo[st_name]
+                e["measured_over_algorithmic"] = e["bytes"] / algo[st_name] if algo[st_name] else None
+        out["ep" if order == "ep" else "default"] = res
+        out[("ep" if order == "ep" else "default") + "_bytes_per_edge"] = sum(v["bytes"] for v in res.values()) / m
+    return out
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +241,8 @@ def _args():
                     help="print a markdown summary of a rocprofv3 kernel trace of this script and exit (no GPU)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print a markdown summary of rocprofv3 counter collections of this script and exit (no GPU)")
+    ap.add_argument("--traffic-json", nargs="+", metavar=("WORKLOAD", "CSV"),
+                    help="print the per-launch traffic JSON of a mesh workload from counter CSVs and exit (no GPU)")
     return ap.parse_args()
 
 
@@ -471,8 +555,18 @@ class _nullctx:
         return False
 
 
-def cpu_baseline_spmv(R, budget_s):
-    """The FP64 oracle SpMV (numpy bincount, one thread) over the whole R-MAT matrix, repeated."""
+def _err(got, ref, A):
+    d = np.abs(np.asarray(got, np.float64) - ref)
+    den = np.abs(ref) + A
+    return {"max_abs": float(d.max()) if d.size else 0.0,
+            "max_rel_floored": float((d / np.where(den > 0, den, 1)).max()) if d.size else 0.0,
+            "normwise": float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300)),
+            "bar": "elementwise |d| <= 1e-5 (|ref| + A), normwise <= 1e-5"}
+
+
+def cpu_baseline_spmv(R, budget_s, gpu_y=None):
+    """The FP64 oracle SpMV (numpy bincount, one thread) over the whole R-MAT matrix, repeated;
+    with gpu_y (original row order) the GPU result's error against it, over every row."""
     from threadpoolctl import threadpool_limits
 
     from gen.rmat import spmv_graph
@@ -489,9 +583,14 @@ def cpu_baseline_spmv(R, budget_s):
         for _ in range(reps):
             spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
         t = time.perf_counter() - t0
-    return {"value": reps * m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"all {m} nonzeros x {reps} passes, FP64, {t:.1f} s on "
-                      f"{cpu_model()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
+    out = {"value": reps * m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"all {m} nonzeros x {reps} passes, FP64, {t:.1f} s on "
+                     f"{cpu_model()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
+    if gpu_y is not None:
+        ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+        A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+        out["gpu_error_vs_oracle"] = dict(_err(gpu_y, ref, A), sample=f"all {R['n_y']} rows of y")
+    return out
 
 
 def main():
@@ -501,6 +600,9 @@ def main():
         return
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters))
+        return
+    if args.traffic_json:
+        print(json.dumps(traffic_json(args.traffic_json[0], args.traffic_json[1:], args.cap), indent=1))
         return
     global GRAPH_TIMING, COLD_STEPS
     GRAPH_TIMING = not args.eager
@@ -644,9 +746,10 @@ def main():
             del b
         COLD_STEPS = saved_cold
     if traffic:
-        out["l2_miss_bytes_per_edge"] = {o: sum(v["bytes"] * v["launches_per_step"] for v in traffic[o].values()) / m
-                                         for o in ("ep", "default")}
-        out["l2_miss_counters"] = traffic.get("counters", "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch")
+        out["l2_miss_bytes_per_edge"] = {"ep": traffic["ep_bytes_per_edge"], "default": traffic["default_bytes_per_edge"],
+                                         "note": "L2 misses to the fabric (MALL hits included) plus writes, "
+                                                 "from request-size counters; see profiles/"}
+        out["l2_miss_counters"] = traffic["counters"]
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(G, args.cpu_budget_s, ep["outputs"])
     print(json.dumps(out), flush=True)
@@ -787,12 +890,17 @@ def bench_spmv(args, torch):
         auto = layouts["vertex_major" if auto_layout else "part_major"]
         best = min(layouts.values(), key=lambda v: v["ms_per_step"])
         # the partitioned order runs its automatic layout; the baselines are quoted at their best one
-        use = auto if name == "ep" else best
+        use = auto if name.startswith("ep") else best
         res[name] = dict(use, layout="vertex_major" if use is layouts.get("vertex_major") else "part_major",
                          layouts=layouts, adjoint_ms=adj_ms, adjoint_edges_per_s=m / (adj_ms * 1e-3),
                          loads_per_edge=st["loads"] / m, slots_per_edge=st["slots"] / m,
                          plan_seconds=plan_s, partition_seconds=st["partition_seconds"])
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+        if name == "ep_weighted":  # the reported order's y, in original row order, for the oracle check
+            P.set_slot_layout(auto_layout)
+            yv = P.spmv(x).cpu().numpy()
+            gpu_y = np.empty(R["n_y"], dtype=np.float32)
+            gpu_y[perm[R["n_x"]:] - R["n_x"]] = yv
         del P
     ep = res["ep_weighted"]
     dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
@@ -810,7 +918,7 @@ def bench_spmv(args, torch):
                        "frac": ach / HBM_PEAK_GBS, "traffic": None}
     out["orders"] = res
     out["source_sha256"] = source_sha256()
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s, gpu_y)
     print(json.dumps(out), flush=True)
 
 
@@ -834,10 +942,9 @@ def bench_batch(args, torch):
     plan_s = time.perf_counter() - t0
     q = torch.from_numpy(np.concatenate([gen.flux_state(g["n"], seed=i)[p.perm()] for i, (g, p) in
                                          enumerate(zip(graphs, plans))])).cuda()
-    gr = torch.from_numpy(np.concatenate([gen.workloads.grad_seed(g["n"], seed=i)[p.perm()] for i, (g, p) in
-                                          enumerate(zip(graphs, plans))])).cuda()
     r = torch.empty_like(q)
     gq = torch.empty_like(q)
+    gr = r  # L = 1/2 sum r^2 over every graph: the adjoint's upstream gradient is r
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -871,10 +978,23 @@ def bench_batch(args, torch):
     info = B.info()
     algo = info["bytes_fwd"] + info["bytes_bwd"]
     ach = algo / (gpu_ms * 1e-3) / 1e9
+    # one clean step: the outputs the oracle checks (per graph, original vertex order)
+    B.forward(q, out=r)
+    B.backward(q, gr, out=gq)
+    torch.cuda.synchronize()
+    r_all, g_all = r.cpu().numpy(), gq.cpu().numpy()
+    outs = []
+    for i, p in enumerate(plans):
+        sl = slice(int(B.offsets[i]), int(B.offsets[i + 1]))
+        ri, gi = np.empty_like(r_all[sl]), np.empty_like(g_all[sl])
+        ri[p.perm()] = r_all[sl]
+        gi[p.perm()] = g_all[sl]
+        outs.append((ri, gi))
     out = _common(args, "edges/s, batched FLUX5 fwd+bwd over 256 uneven meshes in one launch per pass, HIP-graph replay, 1 MI355X",
                   m / wall, wall * 1e3,
                   {"workload": f"batch256: 256 2D/3D mesh graphs, vertex counts log-uniform in [1024, 65536], "
-                               f"total n={n}, m={m}, one capacity and launch shape autotuned over {{64, 128, 256, 512}} x {{64, 128, 256}} lanes x {{one workgroup per item, pipelined persistent}} by timing the batched launch",
+                               f"total n={n}, m={m}, forward then adjoint of L = 1/2 sum r^2 (upstream gradient r), "
+                               f"one capacity and launch shape autotuned over {{64, 128, 256, 512}} x {{64, 128, 256}} lanes x {{one workgroup per item, pipelined persistent}} by timing the batched launch",
                                "graphs": 256, "timing": "the timed steps captured in one HIP graph, one replay"})
     kind = "one workgroup per item" if info["direct"] else "pipelined persistent"
     out["roofline"] = {"bound": "hbm", "kernel": f"graph replay (fwd + reduce + bwd + reduce, {kind})",
@@ -885,33 +1005,46 @@ def bench_batch(args, torch):
                     "caps": {int(c): int((caps == c).sum()) for c in np.unique(caps)}, "gpu_ms_per_step": gpu_ms,
                     "algorithmic_bytes_per_step": algo, "gen_s": gen_s, "autotune_s": tune_s, "plan_s": plan_s}
     out["source_sha256"] = source_sha256()
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_batch(graphs, args.cpu_budget_s)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_batch(graphs, args.cpu_budget_s, outs)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_batch(graphs, budget_s):
-    """The FP64 oracle forward + adjoint (numpy, one thread) over the leading graphs of the batch."""
+def cpu_baseline_batch(graphs, budget_s, gpu_outs=None):
+    """The FP64 oracle forward + adjoint (numpy, one thread) over the leading graphs of the batch;
+    with gpu_outs ((r, g_q) per graph, original order, upstream gradient r) the GPU results'
+    error against it on those graphs."""
     from threadpoolctl import threadpool_limits
 
     import gen
     from oracle import flux
 
     done_m, t = 0, 0.0
+    worst = {"r": [], "g_q": []}
     with threadpool_limits(1):
         for i, g in enumerate(graphs):
             q = gen.flux_state(g["n"], seed=i).astype(np.float64)
-            gr = gen.workloads.grad_seed(g["n"], seed=i).astype(np.float64)
             geom = g["geom"].astype(np.float32).astype(np.float64)
             t0 = time.perf_counter()
-            flux.forward(g["n"], g["edges"], geom, q)
-            flux.backward(g["n"], g["edges"], geom, q, gr)
+            r = flux.forward(g["n"], g["edges"], geom, q)
+            gq = flux.backward(g["n"], g["edges"], geom, q, r)
             t += time.perf_counter() - t0
             done_m += len(g["edges"])
+            if gpu_outs is not None:
+                rA = flux.forward_abs(g["n"], g["edges"], geom, q)
+                worst["r"].append(_err(gpu_outs[i][0], r, rA))
+                worst["g_q"].append(_err(gpu_outs[i][1], gq, flux.backward_abs(g["n"], g["edges"], geom, q,
+                                                                              np.abs(r) + rA)))
             if t > 0.5 * budget_s:
                 break
-    return {"value": done_m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"graphs 0..{i} of {len(graphs)} ({done_m} edges), FP64 forward + adjoint, {t:.1f} s on "
-                      f"{cpu_model()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
+    out = {"value": done_m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"graphs 0..{i} of {len(graphs)} ({done_m} edges), FP64 forward + adjoint, {t:.1f} s on "
+                     f"{cpu_model()} (host reports {os.cpu_count()} CPUs; 1 thread)"}
+    if gpu_outs is not None:
+        out["gpu_error_vs_oracle"] = {
+            k: {f: max(e[f] for e in v) for f in ("max_abs", "max_rel_floored", "normwise")} for k, v in worst.items()}
+        out["gpu_error_vs_oracle"]["sample"] = f"graphs 0..{i}, every vertex (worst over the graphs)"
+        out["gpu_error_vs_oracle"]["bar"] = "elementwise |d| <= 1e-5 (|ref| + A), normwise <= 1e-5"
+    return out
 
 
 if __name__ == "__main__":

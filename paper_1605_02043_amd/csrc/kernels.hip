@@ -681,7 +681,7 @@ __device__ __forceinline__ void sum_store_bwd(const PartHdr &h, const float *vu,
 
 // ---- reduction of one light replicated vertex
 //
-// r_v = (((own + s_1) + s_2) + ...) over at most kHeavySlots partials in
+// r_v = (((own + s_1) + s_2) + ...) over at most kHeavySlots (64) partials in
 // ascending part order, then q_new.  A part-major workspace lists a vertex's
 // slots in its record (up to kRecSlots) or through rslot; a vertex-major one
 // keeps them as one run.  DEV: the owner partial and the slots are read at
