@@ -67,7 +67,9 @@ def _short_name(name: str) -> str:
 
 
 def _is_scrub(name: str, grid: int) -> bool:
-    return "at::native::reduce_kernel" in name and grid >= (1 << 16)
+    """The cache scrub's dispatch (torch's row-sum kernel over the 1 GiB buffer; bench.py runs
+    no other torch reduction)."""
+    return "at::native::reduce_kernel" in name
 
 
 def summarize_trace(path: str) -> str:
@@ -102,26 +104,31 @@ def summarize_trace(path: str) -> str:
 
 
 def summarize_counters(paths) -> str:
-    """Markdown summary of rocprofv3 counter collections (CSV) of bench.py: per library kernel and
-    grid size, the mean value of every counter per dispatch (counters accumulate over the
-    device's XCDs and channels as rocprofv3 reports them)."""
+    """Markdown summary of rocprofv3 counter collections (CSV) of bench.py: per kernel and grid
+    size, the mean value of every counter per dispatch (counters accumulate over the device's
+    XCDs and channels as rocprofv3 reports them), and the bytes and L2 hit rate they give."""
     import csv
 
     acc = {}
     for path in paths:
         with open(path) as f:
             for r in csv.DictReader(f):
-                if "epk::" not in r["Kernel_Name"] and "at::native" not in r["Kernel_Name"]:
-                    continue
                 wg = max(int(r["Workgroup_Size"]), 1)
                 key = (_short_name(r["Kernel_Name"]), int(r["Grid_Size"]) // wg)
                 d = acc.setdefault(key, {})
                 d.setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
     names = sorted({c for d in acc.values() for c in d})
-    out = ["| kernel | workgroups | dispatches | " + " | ".join(names) + " |", "|---|---|---|" + "---|" * len(names)]
+    derived = (("read_bytes", "read MB"), ("write_bytes", "write MB"), ("fetch_size_expression_bytes", "FETCH_SIZE expr MB"),
+               ("l2_hit_rate", "L2 hit"))
+    out = ["| kernel | workgroups | dispatches | " + " | ".join(names) + " | " + " | ".join(h for _, h in derived) + " |",
+           "|---|---|---|" + "---|" * (len(names) + len(derived))]
     for (name, nwg), d in sorted(acc.items()):
         nd = max(len(v) for v in d.values())
-        vals = [f"{np.mean(list(d[c].values())):.6g}" if c in d else "-" for c in names]
+        mean = {c: float(np.mean(list(v.values()))) for c, v in d.items()}
+        vals = [f"{mean[c]:.6g}" if c in mean else "-" for c in names]
+        b = _bytes_of(mean)
+        vals += [("-" if key not in b else f"{b[key]:.3f}" if key == "l2_hit_rate" else f"{b[key] / 1e6:.1f}")
+                 for key, _ in derived]
         out.append(f"| {name} | {nwg} | {nd} | " + " | ".join(vals) + " |")
     return "\n".join(out)
 
@@ -163,6 +170,17 @@ def _bytes_of(c):
     return out
 
 
+PMC_PASSES = (("R", "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"),
+              ("W", "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_BUBBLE_sum"),
+              ("H", "TCC_HIT_sum TCC_MISS_sum"))
+
+
+def pmc_commands(name: str, bench_args: str) -> list:
+    """The three counter passes (one rocprofv3 run each) whose CSVs a traffic summary reads."""
+    return [f"timeout -s KILL 400 rocprofv3 --pmc {ctr} --output-format csv -d <dir>/{name}_{p} -o {name} "
+            f"-- python3 bench.py {bench_args}" for p, ctr in PMC_PASSES]
+
+
 def traffic_json(workload: str, paths, cap: int = 256) -> dict:
     """Per-launch L2-miss traffic (reads to the fabric, MALL hits included, and writes) of the
     partitioned and default-order kernels of a mesh workload, from counter CSVs of
@@ -176,7 +194,9 @@ def traffic_json(workload: str, paths, cap: int = 256) -> dict:
     out = {"source_sha256": source_sha256(), "workload": workload,
            "counters": "TCC_EA0_RDREQ{,_32B,_64B,_128B}_sum, TCC_EA0_WRREQ{,_64B}_sum, TCC_BUBBLE_sum, "
                        "TCC_HIT_sum, TCC_MISS_sum per dispatch (rocprofv3 --pmc, three passes); bytes = L2 misses to "
-                       "the fabric by request size (MALL hits included) plus writes"}
+                       "the fabric by request size (MALL hits included) plus writes",
+           "commands": pmc_commands(workload, ("" if workload == "tet55" else f"--workload {workload} ")
+                                    + "--eager --steps 3 --warmup 1 --cold-steps 0 --no-cpu-baseline --no-baselines")}
     for order in ("ep", "input"):
         P = Plan(G["edges"], G["n"], cap, G["geom"].astype(np.float32), order=order)
         info, st = P.info(), P.stats
@@ -205,6 +225,43 @@ def traffic_json(workload: str, paths, cap: int = 256) -> dict:
                 e["measured_over_algorithmic"] = e["bytes"] / algo[st_name] if algo[st_name] else None
         out["ep" if order == "ep" else "default"] = res
         out[("ep" if order == "ep" else "default") + "_bytes_per_edge"] = sum(v["bytes"] for v in res.values()) / m
+    return out
+
+
+SPMV_ORDERS = ("ep_weighted", "ep", "shuffled", "row_sorted")  # the order bench_spmv runs them in
+
+
+def spmv_traffic_json(paths) -> dict:
+    """Per-launch L2-miss traffic of the SpMV kernels of `bench.py --workload rmat20` counter runs,
+    per task order.  The orders run one after another with the same number of launches each, so a
+    kernel's dispatches, in dispatch order, split into equal consecutive runs, one per order."""
+    import csv
+
+    per = {}  # (kernel, file) -> {dispatch: {counter: value}}
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = _short_name(r["Kernel_Name"])
+                if not name.startswith(("spmv_kernel", "spmv_adj_kernel", "reduce_kernel")):
+                    continue
+                per.setdefault((name, path), {}).setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = \
+                    float(r["Counter_Value"])
+    acc = {}
+    for (name, path), disp in per.items():
+        ids = sorted(disp)
+        n_per = len(ids) // len(SPMV_ORDERS)
+        for i, order in enumerate(SPMV_ORDERS):
+            for d in ids[i * n_per:(i + 1) * n_per]:
+                for c, v in disp[d].items():
+                    acc.setdefault((order, name), {}).setdefault(c, []).append(v)
+    out = {"source_sha256": source_sha256(), "workload": "rmat20",
+           "counters": "request-size counters per dispatch as for tet55; dispatches split per order by dispatch order",
+           "commands": pmc_commands("rmat20", "--workload rmat20 --steps 3 --warmup 1 --no-cpu-baseline")}
+    for (order, name), cs in sorted(acc.items()):
+        b = _bytes_of({c: float(np.mean(v)) for c, v in cs.items()})
+        b["bytes"] = b.get("read_bytes", 0.0) + b.get("write_bytes", 0.0)
+        b["dispatches"] = max(len(v) for v in cs.values())
+        out.setdefault(order, {})[name] = b
     return out
 
 
@@ -241,6 +298,8 @@ def _args():
                     help="print a markdown summary of a rocprofv3 kernel trace of this script and exit (no GPU)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print a markdown summary of rocprofv3 counter collections of this script and exit (no GPU)")
+    ap.add_argument("--spmv-traffic-json", nargs="+", metavar="CSV",
+                    help="print the per-order SpMV traffic JSON from rmat20 counter CSVs and exit (no GPU)")
     ap.add_argument("--traffic-json", nargs="+", metavar=("WORKLOAD", "CSV"),
                     help="print the per-launch traffic JSON of a mesh workload from counter CSVs and exit (no GPU)")
     return ap.parse_args()
@@ -284,6 +343,21 @@ def _stage(P, torch, i, q, gr, r, gq):
     check(lib.epk_run_stage(P._h, op, stage, _dptr(q), _dptr(b), _dptr(out), 0.0, None, _dptr(P.workspace), h))
 
 
+def _stage_timed(P, torch, i, q, gr, r, gq) -> float:
+    """Stage i alone (as _stage), timed by the kernel's own dispatch timestamps: ms as the GPU ran it."""
+    import ctypes
+
+    from paper_1605_02043_amd._lib import check, lib
+    from paper_1605_02043_amd.plan import _dptr
+
+    op, stage, b, out = [(0, 0, None, r), (0, 1, None, r), (1, 0, gr, gq), (1, 1, gr, gq)][i]
+    h = C_void(torch.cuda.current_stream().cuda_stream)
+    ms = ctypes.c_float()
+    check(lib.epk_run_stage_timed(P._h, op, stage, _dptr(q), _dptr(b), _dptr(out), 0.0, None, _dptr(P.workspace), h,
+                                  ctypes.byref(ms)))
+    return float(ms.value)
+
+
 def C_void(x):
     import ctypes
 
@@ -291,13 +365,16 @@ def C_void(x):
 
 
 def make_scrub(torch):
-    """Read-only cache scrub: a sum over 1 GiB (4x the 256 MiB MALL, 256x an XCD's 4 MiB L2).
-    It leaves no dirty lines behind, so the kernel timed after it pays only for its own misses."""
-    buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    out = torch.empty((), dtype=torch.float32, device="cuda")
+    """Read-only cache scrub: row sums of a 1 GiB buffer (4x the 256 MiB MALL, 256x an XCD's
+    4 MiB L2), 65536 rows, so that every CU of every XCD streams its share (a full reduction to
+    one value runs in a single workgroup and evicts one XCD's L2 only).  It writes 256 KiB of
+    sums and leaves no other dirty lines, so the kernel timed after it pays only for its own
+    misses."""
+    buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda").view(1 << 16, 1 << 12)
+    out = torch.empty(1 << 16, dtype=torch.float32, device="cuda")
 
     def scrub():
-        torch.sum(buf, dim=0, out=out)
+        torch.sum(buf, dim=1, out=out)
 
     return scrub, buf
 
@@ -407,20 +484,23 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, sta
             e1.record()
         torch.cuda.synchronize()
         loop[nm] = e0.elapsed_time(e1) / steps
+    # each stage alone, K launches timed by their own dispatch timestamps (the kernel's duration as
+    # a kernel trace reports it), each after a launch of the same stage: warm caches
+    kernel_warm = {}
+    for i, nm in enumerate(names):
+        _stage(P, torch, i, q, gr, r, gq)
+        kernel_warm[nm] = _med([_stage_timed(P, torch, i, q, gr, r, gq) for _ in range(steps)])
     cold = None
     if scrub is not None and COLD_STEPS > 0:
-        # cold caches: the read-only scrub before every timed launch (each kernel alone, then
-        # whole steps with the per-kernel split)
+        # cold caches: the read-only scrub before every timed launch (each kernel alone, timed by its
+        # dispatch timestamps, then whole steps with the per-kernel split by events)
         cold = {}
         for i, nm in enumerate(names):
-            ce = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(COLD_STEPS)]
-            for a, b in ce:
+            ts = []
+            for _ in range(COLD_STEPS):
                 scrub()
-                a.record()
-                _stage(P, torch, i, q, gr, r, gq)
-                b.record()
-            torch.cuda.synchronize()
-            cold[nm] = _med([a.elapsed_time(b) for a, b in ce])
+                ts.append(_stage_timed(P, torch, i, q, gr, r, gq))
+            cold[nm] = _med(ts)
         cev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(COLD_STEPS)]
         for i in range(COLD_STEPS):
             scrub()
@@ -444,6 +524,7 @@ def run_order(G, order, cap, steps, warmup, torch, wg=0, swizzle=1, pipe=-1, sta
         "gpu_ms_per_step": step_gpu,
         "kernel_ms": dur,
         "kernel_loop_ms": loop,
+        "kernel_warm_ms": kernel_warm,
         "info": info,
         "stats": st,
         "plan_seconds": plan_s,
@@ -601,6 +682,9 @@ def main():
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters))
         return
+    if args.spmv_traffic_json:
+        print(json.dumps(spmv_traffic_json(args.spmv_traffic_json), indent=1))
+        return
     if args.traffic_json:
         print(json.dumps(traffic_json(args.traffic_json[0], args.traffic_json[1:], args.cap), indent=1))
         return
@@ -643,26 +727,31 @@ def main():
     # dominant kernel of the partitioned step
     k_ms = ep["kernel_ms"]
     lp_ms = ep["kernel_loop_ms"]
-    dom = max(lp_ms, key=lp_ms.get)
+    kw_ms = ep["kernel_warm_ms"]
+    dom = max(kw_ms, key=kw_ms.get)
     info = ep["info"]
     algo = {"flux_fwd": info["bytes_fwd_kernel"], "flux_bwd": info["bytes_bwd_kernel"],
             "reduce_fwd": info["bytes_fwd"] - info["bytes_fwd_kernel"],
             "reduce_bwd": info["bytes_bwd"] - info["bytes_bwd_kernel"]}
-    warm_achieved = algo[dom] / (lp_ms[dom] * 1e-3) / 1e9
+    warm_achieved = algo[dom] / (kw_ms[dom] * 1e-3) / 1e9
+    b2b_achieved = algo[dom] / (lp_ms[dom] * 1e-3) / 1e9
     cold = ep["cold_ms"]
     traffic = measured_traffic(args.workload)
-    per_kernel = {nm: {"ms_in_step": k_ms[nm], "ms": lp_ms[nm], "algorithmic_bytes": algo[nm],
-                       "GB/s": algo[nm] / (lp_ms[nm] * 1e-3) / 1e9} for nm in k_ms}
+    per_kernel = {nm: {"ms_in_step": k_ms[nm], "ms": kw_ms[nm], "ms_back_to_back": lp_ms[nm],
+                       "algorithmic_bytes": algo[nm], "GB/s": algo[nm] / (kw_ms[nm] * 1e-3) / 1e9} for nm in k_ms}
     if cold:
         for nm in per_kernel:
             per_kernel[nm]["ms_cold"] = cold[nm]
             per_kernel[nm]["GB/s_cold"] = algo[nm] / (cold[nm] * 1e-3) / 1e9
-    warm_timing = (f"HIP events around a HIP-graph replay of {args.steps} back-to-back launches of the kernel"
-                   if GRAPH_TIMING else f"HIP events around {args.steps} back-to-back launches of the kernel")
+    warm_timing = (f"median of {args.steps} launches of the kernel, each right after the previous one, timed by "
+                   f"the dispatch's own timestamps")
+    b2b_timing = (f"HIP events around a HIP-graph replay of {args.steps} back-to-back launches of the kernel "
+                  f"(kernel plus the gap between launches)" if GRAPH_TIMING
+                  else f"HIP events around {args.steps} back-to-back launches of the kernel")
     if cold:
         achieved = algo[dom] / (cold[dom] * 1e-3) / 1e9
-        timing = (f"median of {COLD_STEPS} launches of the kernel, each after a read-only 1 GiB scrub "
-                  f"(HIP events on the launch stream)")
+        timing = (f"median of {COLD_STEPS} launches of the kernel, each after a read-only 1 GiB scrub, timed by "
+                  f"the dispatch's own timestamps (hipExtLaunchKernel events)")
     else:
         achieved, timing = warm_achieved, warm_timing
     st = ep["stats"]
@@ -700,7 +789,9 @@ def main():
                      "traffic": traffic["ep"][dom]["bytes"] if traffic else None,
                      "warm": {"achieved": warm_achieved, "frac": warm_achieved / HBM_PEAK_GBS, "timing": warm_timing,
                               "note": "the step's working set fits the 256 MiB MALL, so back-to-back launches "
-                                      "are served partly from it"}},
+                                      "are served partly from it"},
+                     "back_to_back": {"achieved": b2b_achieved, "frac": b2b_achieved / HBM_PEAK_GBS,
+                                      "timing": b2b_timing}},
         "kernels": per_kernel,
         "gpu_ms_per_step": ep["gpu_ms_per_step"],
         "replays": ep["replays"],
@@ -803,6 +894,8 @@ def _common(args, metric, value, ms, config):
 
 def bench_spmv(args, torch):
     """R-MAT 2^20 x 2^20, 2^24 nonzeros: SpMV in partitioned vs shuffled vs row-sorted order."""
+    import ctypes
+
     import gen
     from gen.rmat import spmv_graph
     from paper_1605_02043_amd import Plan
@@ -812,9 +905,11 @@ def bench_spmv(args, torch):
     R = gen.rmat(20, 1 << 24, seed=0)
     m = len(R["rows"])
     res = {}
-    for name, perm_e, order, cw in (("ep_weighted", R["shuffle"], "ep", (1, SPMV_Y_WEIGHT)),
-                                    ("ep", R["shuffle"], "ep", None), ("shuffled", R["shuffle"], "input", None),
-                                    ("row_sorted", np.argsort(R["rows"], kind="stable"), "input", None)):
+    setups = {"ep_weighted": (R["shuffle"], "ep", (1, SPMV_Y_WEIGHT)), "ep": (R["shuffle"], "ep", None),
+              "shuffled": (R["shuffle"], "input", None),
+              "row_sorted": (np.argsort(R["rows"], kind="stable"), "input", None)}
+    for name in SPMV_ORDERS:
+        perm_e, order, cw = setups[name]
         g = spmv_graph(R, perm_e)
         t0 = time.perf_counter()
         P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"], class_weight=cw)
@@ -868,11 +963,20 @@ def bench_spmv(args, torch):
                 torch.cuda.synchronize()
                 wall = (time.perf_counter() - t0) / args.steps
                 del g
+            # each kernel by its own dispatch timestamps (the duration a kernel trace reports), median
+            kt = [[], []]
+            for _ in range(args.steps):
+                for i in range(2):
+                    ms = ctypes.c_float()
+                    check(lib.epk_run_stage_timed(P._h, 2, i, _dptr(x), None, _dptr(y), 0.0, None, ws, h,
+                                                  ctypes.byref(ms)))
+                    kt[i].append(ms.value)
             info = P.info()
             layouts["vertex_major" if layout else "part_major"] = {
                 "edges_per_s": m / wall, "ms_per_step": wall * 1e3,
-                "kernels_ms": {"spmv": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
-                               "reduce": float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))},
+                "kernels_ms": {"spmv": _med(kt[0]), "reduce": _med(kt[1])},
+                "kernels_ms_in_step": {"spmv": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                                       "reduce": float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))},
                 "algorithmic_bytes": {"spmv": info["bytes_fwd_kernel"],
                                       "reduce": info["bytes_fwd"] - info["bytes_fwd_kernel"]}}
         # the adjoint (g_x = A^T g_y) on the same plan
@@ -914,8 +1018,12 @@ def bench_spmv(args, torch):
                                       "timing": ("step: the timed steps captured in one HIP graph, one replay; "
                                                  "kernels: HIP events in eager steps") if GRAPH_TIMING
                                       else "HIP events in eager steps"})
+    traffic = measured_traffic("rmat20")
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                       "frac": ach / HBM_PEAK_GBS,
+                       "timing": f"median of {args.steps} launches, timed by the dispatch's own timestamps",
+                       "traffic": (traffic["ep_weighted"][{"spmv": "spmv_kernel", "reduce": "reduce_kernel<1, false>"}[dom]]
+                                   ["bytes"] if traffic and "ep_weighted" in traffic else None)}
     out["orders"] = res
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s, gpu_y)

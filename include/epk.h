@@ -288,6 +288,17 @@ int epk_spmv(const epk_plan *p, const float *x, float *y, void *d_ws, void *stre
  * backward/spmv).                                                         */
 int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                   float dt, float *q_new, void *d_ws, void *stream);
+/* epk_run_stage for benchmarking the stage's kernel (the measurements of
+ * Section 5 are kernel times): the kernel is launched with start and stop
+ * events that take the dispatch's own timestamps (hipExtLaunchKernel), and
+ * *ms (host) receives its duration as the GPU ran it, without the dispatch
+ * latency and event overheads that events recorded around the call would
+ * add.  Blocks the host until the kernel ends; work enqueued earlier on the
+ * stream (a cache scrub, say) runs first and is not counted.  *ms = 0 if the
+ * stage launches no kernel.  Not for use under stream capture.  EPK_EINVAL
+ * for a NULL ms; other errors as epk_run_stage.                          */
+int epk_run_stage_timed(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
+                        float dt, float *q_new, void *d_ws, void *stream, float *ms);
 /* op codes of epk_run_stage */
 /* SpMV adjoint on the same plan (Section 5.2's graph, transposed; the
  * paper has no adjoint): g_x = A^T g_y (g_x[j] = sum over the

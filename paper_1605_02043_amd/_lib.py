@@ -72,6 +72,8 @@ _SIGS = {
     "epk_spmv": (C.c_int, [_P, _FP, _FP, _P, _P]),
     "epk_spmv_adjoint": (C.c_int, [_P, _FP, _FP, _FP, _FP, _P, _P]),
     "epk_run_stage": (C.c_int, [_P, C.c_int32, C.c_int32, _FP, _FP, _FP, C.c_float, _FP, _P, _P]),
+    "epk_run_stage_timed": (C.c_int, [_P, C.c_int32, C.c_int32, _FP, _FP, _FP, C.c_float, _FP, _P, _P,
+                                      C.POINTER(C.c_float)]),
     "epk_permute_rows": (C.c_int, [_FP, _FP, _P, C.c_int64, C.c_int32, C.c_int32, _P]),
     "epk_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
     "epk_batch_device_bytes": (C.c_int, [_P, _SZP, _SZP]),

@@ -588,6 +588,35 @@ int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in,
   return run_stage(p, op, stage, in, g_r, out, dt, q_new, d_ws, stream);
 }
 
+int epk_run_stage_timed(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
+                        float dt, float *q_new, void *d_ws, void *stream, float *ms) {
+  clear_error();
+  if (!ms) return fail(EPK_EINVAL, "ms is NULL");
+  *ms = 0.f;
+  if (stage != 0 && stage != 1) return fail(EPK_EINVAL, "stage must be 0 or 1");
+  if (!p) return fail(EPK_EINVAL, "plan is NULL");
+  if (!p->d_image) return fail(EPK_ESTATE, "plan not uploaded");
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    if (a) hipEventDestroy(a);
+    return hip_status(e, "event create");
+  }
+  g_timing = LaunchTiming{a, b, 0};
+  int st = run_stage(p, op, stage, in, g_r, out, dt, q_new, d_ws, stream);
+  const int launched = g_timing.launched;
+  g_timing = LaunchTiming{};
+  if (st == EPK_OK && launched > 0) {
+    e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (e != hipSuccess) st = hip_status(e, "kernel timing");
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return st;
+}
+
 int epk_forward(const epk_plan *p, const float *q, float *r, float dt, float *q_new, void *d_ws, void *stream) {
   clear_error();
   return run_stage(p, EPK_OP_FORWARD, -1, q, nullptr, r, dt, q_new, d_ws, stream);

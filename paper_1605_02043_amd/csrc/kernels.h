@@ -7,6 +7,15 @@
 
 namespace epk {
 
+// Dispatch timestamps for benchmarking: while `start` is set, the launchers on this thread pass
+// start/stop to hipExtLaunchKernel, which records the kernel's own start and end times into them;
+// `launched` counts those launches.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int launched = 0;
+};
+extern thread_local LaunchTiming g_timing;
+
 int grid_of_parts(int k, int swizzle);
 // fused: the single-launch reduction (the plan's signal records and counters are set in P)
 hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q, float *r, float *qn, float dt,

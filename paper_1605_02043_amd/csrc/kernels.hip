@@ -13,6 +13,7 @@
 // A reduction kernel then adds, for every replicated vertex, the slots to the
 // owner's partial in ascending part order.  Nothing uses atomics on data, so
 // every result is bitwise reproducible.  No MFMA: the work is gather/scatter.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "epk_internal.h"
@@ -1486,6 +1487,21 @@ int edges_per_thread(int cap, int wg) {
   return e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : e <= 8 ? 8 : -1;
 }
 
+thread_local LaunchTiming g_timing;
+
+// A kernel launch; with g_timing set, through hipExtLaunchKernelGGL so that the events take the
+// dispatch's own timestamps.
+#define EPK_LAUNCH(K, grid, block, lds, s, ...)                                                  \
+  do {                                                                                           \
+    if (g_timing.start) {                                                                        \
+      hipExtLaunchKernelGGL(K, grid, block, uint32_t(lds), s, g_timing.start, g_timing.stop, 0u, \
+                            __VA_ARGS__);                                                        \
+      ++g_timing.launched;                                                                       \
+    } else {                                                                                     \
+      hipLaunchKernelGGL(K, grid, block, lds, s, __VA_ARGS__);                                   \
+    }                                                                                            \
+  } while (0)
+
 #define EPK_EPT_SWITCH(ept, CALL) \
   switch (ept) {                  \
     case 1: {                     \
@@ -1515,7 +1531,7 @@ hipError_t launch_flux_fwd(const DevPlan &P, int wg, size_t lds, const float *q,
   const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
   const int ept = edges_per_thread(P.cap, wg);
 #define EPK_FWD(G, QN, F) \
-  EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_kernel<G, QN, E, F>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle))
+  EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_fwd_kernel<G, QN, E, F>), grid, block, lds, s, P, q, r, qn, dt, ws, swizzle))
   if (P.geom_ncomp == 4) {
     if (qn) {
       if (fused) { EPK_FWD(4, true, true) } else { EPK_FWD(4, true, false) }
@@ -1539,7 +1555,7 @@ hipError_t launch_flux_bwd(const DevPlan &P, int wg, size_t lds, const float *q,
   const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
   const int ept = edges_per_thread(P.cap, wg);
 #define EPK_BWD(G, F) \
-  EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_kernel<G, E, F>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
+  EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_bwd_kernel<G, E, F>), grid, block, lds, s, P, q, gr, gq, ws, swizzle))
   if (P.geom_ncomp == 4) {
     if (fused) { EPK_BWD(4, true) } else { EPK_BWD(4, false) }
   } else {
@@ -1556,24 +1572,24 @@ hipError_t launch_flux_cached(const DevPlan &P, int wg, size_t lds, const float 
   const int ept = edges_per_thread(P.cap, wg);
   if (backward) {
     if (P.geom_ncomp == 4) {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_cached<4, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_bwd_cached<4, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
     } else {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_bwd_cached<2, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_bwd_cached<2, E>), grid, block, lds, s, P, q, gr, out, ws, swizzle))
     }
   } else if (P.geom_ncomp == 4) {
     if (qn) {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<4, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_fwd_cached<4, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
                                              swizzle))
     } else {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<4, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_fwd_cached<4, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
                                              swizzle))
     }
   } else {
     if (qn) {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<2, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_fwd_cached<2, true, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
                                              swizzle))
     } else {
-      EPK_EPT_SWITCH(ept, hipLaunchKernelGGL((flux_fwd_cached<2, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
+      EPK_EPT_SWITCH(ept, EPK_LAUNCH((flux_fwd_cached<2, false, E>), grid, block, lds, s, P, q, out, qn, dt, ws,
                                              swizzle))
     }
   }
@@ -1605,25 +1621,27 @@ hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, cons
   const void *fn = pipe_fn(backward, P.geom_ncomp, qn != nullptr, edges_per_thread(P.cap, wg));
   if (!fn || grid < 1 || (swizzle && grid % 8)) return hipErrorInvalidValue;
   DevPlan Pa = P;
-  if (backward) {
-    void *args[] = {&Pa, &q, &gr, &out, &ws, &swizzle};
-    return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, lds, s);
+  void *args_bwd[] = {&Pa, &q, &gr, &out, &ws, &swizzle};
+  void *args_fwd[] = {&Pa, &q, &out, &qn, &dt, &ws, &swizzle};
+  void **args = backward ? args_bwd : args_fwd;
+  if (g_timing.start) {
+    ++g_timing.launched;
+    return hipExtLaunchKernel(fn, dim3(grid), dim3(wg), args, lds, s, g_timing.start, g_timing.stop, 0);
   }
-  void *args[] = {&Pa, &q, &out, &qn, &dt, &ws, &swizzle};
   return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, lds, s);
 }
 
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
                        hipStream_t s) {
   if (P.k == 0) return hipSuccess;
-  hipLaunchKernelGGL(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
+  EPK_LAUNCH(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
   return hipGetLastError();
 }
 
 hipError_t launch_spmv_adjoint(const DevPlan &P, int wg, size_t lds, const float *x, const float *gy, float *gx,
                                float *gw, float *ws, int swizzle, hipStream_t s) {
   if (P.k == 0) return hipSuccess;
-  hipLaunchKernelGGL(spmv_adj_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, gy, gx, gw, ws,
+  EPK_LAUNCH(spmv_adj_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, gy, gx, gw, ws,
                      swizzle);
   return hipGetLastError();
 }
@@ -1636,12 +1654,12 @@ hipError_t launch_reduce(const DevPlan &P, int nc, float *r, const float *ws, co
   if (grid == 0) return hipSuccess;
   if (nc == 5) {
     if (qn)
-      hipLaunchKernelGGL((reduce_kernel<5, true>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt, nb_light);
+      EPK_LAUNCH((reduce_kernel<5, true>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt, nb_light);
     else
-      hipLaunchKernelGGL((reduce_kernel<5, false>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt,
+      EPK_LAUNCH((reduce_kernel<5, false>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt,
                          nb_light);
   } else {
-    hipLaunchKernelGGL((reduce_kernel<1, false>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt, nb_light);
+    EPK_LAUNCH((reduce_kernel<1, false>), dim3(grid), dim3(kReduceBlock), 0, s, P, r, ws, q, qn, dt, nb_light);
   }
   return hipGetLastError();
 }

@@ -86,6 +86,11 @@ def test_device_calls_refuse_before_upload():
     assert lib.epk_forward(P._h, None, None, 0.0, None, None, None) == _lib.EPK_ESTATE
     assert lib.epk_backward(P._h, None, None, None, None, None) == _lib.EPK_ESTATE
     assert lib.epk_spmv(P._h, None, None, None, None) == _lib.EPK_ESTATE  # wrong kind
+    ms = C.c_float(-1.0)
+    assert lib.epk_run_stage_timed(P._h, 0, 0, None, None, None, 0.0, None, None, None, C.byref(ms)) == _lib.EPK_ESTATE
+    assert ms.value == 0.0
+    assert lib.epk_run_stage_timed(P._h, 0, 0, None, None, None, 0.0, None, None, None, None) == _lib.EPK_EINVAL
+    assert lib.epk_run_stage_timed(P._h, 0, 2, None, None, None, 0.0, None, None, None, C.byref(ms)) == _lib.EPK_EINVAL
     with pytest.raises(_lib.EpkError):
         P.set_launch(wg=100)
 
