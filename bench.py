@@ -31,6 +31,7 @@ GRAPH_TIMING = True  # cleared by --eager
 COLD_STEPS = 20  # set by --cold-steps
 REPLAYS = 20  # timed replays of the K-step graph for the spread
 SPMV_Y_WEIGHT = 4  # SpMV partition: a replicated y (partial, reduction) weighs 4 replicated x (one gather)
+SPMV_HUB_DEGREE = 16  # SpMV partition: rows above 16 nonzeros go to the hub split
 CSRC = os.path.join(ROOT, "paper_1605_02043_amd", "csrc")
 
 
@@ -228,7 +229,8 @@ def traffic_json(workload: str, paths, cap: int = 256) -> dict:
     return out
 
 
-SPMV_ORDERS = ("ep_weighted", "ep", "shuffled", "row_sorted")  # the order bench_spmv runs them in
+SPMV_ORDERS = ("ep_hub", "ep_weighted", "ep", "shuffled", "row_sorted")  # the order bench_spmv runs them in
+SPMV_HEADLINE = "ep_hub"
 
 
 def spmv_traffic_json(paths) -> dict:
@@ -905,14 +907,16 @@ def bench_spmv(args, torch):
     R = gen.rmat(20, 1 << 24, seed=0)
     m = len(R["rows"])
     res = {}
-    setups = {"ep_weighted": (R["shuffle"], "ep", (1, SPMV_Y_WEIGHT)), "ep": (R["shuffle"], "ep", None),
-              "shuffled": (R["shuffle"], "input", None),
-              "row_sorted": (np.argsort(R["rows"], kind="stable"), "input", None)}
+    setups = {"ep_hub": (R["shuffle"], "ep", (1, SPMV_Y_WEIGHT), SPMV_HUB_DEGREE),
+              "ep_weighted": (R["shuffle"], "ep", (1, SPMV_Y_WEIGHT), 0), "ep": (R["shuffle"], "ep", None, 0),
+              "shuffled": (R["shuffle"], "input", None, 0),
+              "row_sorted": (np.argsort(R["rows"], kind="stable"), "input", None, 0)}
     for name in SPMV_ORDERS:
-        perm_e, order, cw = setups[name]
+        perm_e, order, cw, hub = setups[name]
         g = spmv_graph(R, perm_e)
         t0 = time.perf_counter()
-        P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"], class_weight=cw)
+        P = Plan(g["edges"], g["n"], args.cap, g["w"], order=order, kind="spmv", n_x=g["n_x"], class_weight=cw,
+                 hub_degree=hub)
         P.set_launch(args.wg, args.swizzle)
         P.upload("cuda")
         plan_s = time.perf_counter() - t0
@@ -1000,30 +1004,32 @@ def bench_spmv(args, torch):
                          loads_per_edge=st["loads"] / m, slots_per_edge=st["slots"] / m,
                          plan_seconds=plan_s, partition_seconds=st["partition_seconds"])
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
-        if name == "ep_weighted":  # the reported order's y, in original row order, for the oracle check
+        if name == SPMV_HEADLINE:  # the reported order's y, in original row order, for the oracle check
             P.set_slot_layout(auto_layout)
             yv = P.spmv(x).cpu().numpy()
             gpu_y = np.empty(R["n_y"], dtype=np.float32)
             gpu_y[perm[R["n_x"]:] - R["n_x"]] = yv
         del P
-    ep = res["ep_weighted"]
+    ep = res[SPMV_HEADLINE]
     dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
     ach = ep["algorithmic_bytes"][dom] / (ep["kernels_ms"][dom] * 1e-3) / 1e9
     out = _common(args, "edges/s, SpMV y += A x, partitioned vs shuffled order, 1 MI355X", ep["edges_per_s"],
                   ep["ms_per_step"], {"workload": f"rmat20: R-MAT 2^20 x 2^20, {m} nonzeros (a,b,c)=(0.57,0.19,0.19), "
                                                   f"w~U[0,1), x~N(0,1), capacity {args.cap}, partitioned order "
-                                                  f"(EP with y copies weighing {SPMV_Y_WEIGHT}; the uniform-weight EP "
-                                                  f"order is under orders.ep)",
+                                                  f"(the rows above {SPMV_HUB_DEGREE} nonzeros in runs of the "
+                                                  f"capacity, the rest EP with y copies weighing {SPMV_Y_WEIGHT}; "
+                                                  f"EP without the split under orders.ep_weighted, uniform weights "
+                                                  f"under orders.ep)",
                                       "capacity": args.cap,
-                                      "timing": ("step: the timed steps captured in one HIP graph, one replay; "
-                                                 "kernels: HIP events in eager steps") if GRAPH_TIMING
-                                      else "HIP events in eager steps"})
+                                      "timing": ("step: the timed steps captured in one HIP graph, one replay"
+                                                 if GRAPH_TIMING else "step: eager launches")
+                                      + "; kernels: median of launches timed by their dispatch timestamps"})
     traffic = measured_traffic("rmat20")
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS,
                        "timing": f"median of {args.steps} launches, timed by the dispatch's own timestamps",
-                       "traffic": (traffic["ep_weighted"][{"spmv": "spmv_kernel", "reduce": "reduce_kernel<1, false>"}[dom]]
-                                   ["bytes"] if traffic and "ep_weighted" in traffic else None)}
+                       "traffic": (traffic[SPMV_HEADLINE][{"spmv": "spmv_kernel", "reduce": "reduce_kernel<1, false>"}[dom]]
+                                   ["bytes"] if traffic and SPMV_HEADLINE in traffic else None)}
     out["orders"] = res
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s, gpu_y)

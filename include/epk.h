@@ -131,12 +131,32 @@ int epk_partition(const epk_graph *g, int32_t capacity, int32_t order, int32_t *
 int epk_partition_weighted(const epk_graph *g, int32_t capacity, int32_t order, const int32_t *class_weight,
                            int32_t *part_of_edge, int32_t *task_order, epk_stats *stats);
 
+/* The EP order after a hub split, for graphs whose degrees follow a power
+ * law (an extension of Section 3.2's partition; the paper has no such
+ * step).  An edge is a hub edge when its class-y endpoint (vertex id >=
+ * g->n_x; of two such endpoints the one of larger degree, ties to the
+ * smaller id) has degree above hub_degree.  The hub edges, sorted by (that
+ * endpoint, the other endpoint, edge id), fill parts 0 .. kh-1 in runs of
+ * `capacity` edges, so a hub of degree d lands in at most ceil(d/capacity)
+ * + 1 parts, a bound the multilevel heuristic does not keep on such
+ * graphs.  The other edges, in ascending id, form a graph that the EP
+ * order (multilevel, with class_weight as in epk_partition_weighted)
+ * splits into parts kh, kh+1, ...; task order: the hub parts, then that
+ * partition's task order.  With no hub edge the result equals
+ * epk_partition_weighted's.  hub_degree >= 1, else EPK_EINVAL; other
+ * arguments and errors as epk_partition_weighted.                        */
+int epk_partition_hub(const epk_graph *g, int32_t capacity, const int32_t *class_weight, int32_t hub_degree,
+                      int32_t *part_of_edge, int32_t *task_order, epk_stats *stats);
+
 /* Plan = partition + data packing along the task order (Section 4.1) + the
  * device image the kernels read.  Host only, synchronous.                */
 int epk_plan_create(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind, epk_plan **out);
 /* epk_plan_create with per-class vertex weights (see epk_partition_weighted). */
 int epk_plan_create_weighted(const epk_graph *g, int32_t capacity, int32_t order, int32_t kind,
                              const int32_t *class_weight, epk_plan **out);
+/* epk_plan_create with the hub-split EP partition (epk_partition_hub).   */
+int epk_plan_create_hub(const epk_graph *g, int32_t capacity, int32_t kind, const int32_t *class_weight,
+                        int32_t hub_degree, epk_plan **out);
 /* The same plan from a partition the caller made (Definition 2's output,
  * e.g. from an offline partitioner): part_of_edge[m] in [0, n_parts);
  * task_order[m] lists the edges part by part, parts ascending (NULL:

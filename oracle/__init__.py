@@ -24,6 +24,9 @@ GPU Caching Problems"):
 * ``baselines`` - PowerGraph's random and greedy vertex-cut placements, the
                 partitioners the paper compares against (Section 3.3).
 * ``brute``   - exhaustive optimal partitions for tiny graphs (Theorems 1-2).
+* ``hub``     - the hub split before the EP order (an extension for power-law
+                graphs, not in the paper; pinned on ``hub_split7.json``, by its
+                reduction to the plain EP order and by invariants).
 
 Parity status: the cost, transform, flux, adjoint and SpMV functions are pinned
 by closed forms, invariants, textbook properties and library routines in the
@@ -46,14 +49,18 @@ parity unpinned: it is fixed by their specification and checked only by two
 independent implementations agreeing bit for bit.
 """
 
-from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines  # noqa: F401
+from . import graph, cost, ggp, multilevel, cpack, flux, spmv, brute, baselines, hub  # noqa: F401
 
 
-def partition(edges, n, cap, order="ep", class_weight=None, n_x=0):
+def partition(edges, n, cap, order="ep", class_weight=None, n_x=0, hub_degree=0):
     """(part, task_order) for an order: 'ep' (multilevel, the default), 'ggp'
     (single-pass greedy growing), 'input' (consecutive blocks), or the
     baselines 'random' and 'greedy'.  class_weight (EP only): per-class vertex
-    weights (x: ids below n_x, y: the rest)."""
+    weights (x: ids below n_x, y: the rest).  hub_degree > 0 (EP only): the hub
+    split first."""
+    if order == "ep" and hub_degree > 0:
+        part, task, _ = hub.partition(edges, n, cap, hub_degree, class_weight, n_x)
+        return part, task
     if order == "ep":
         part, task, _ = multilevel.partition(edges, n, cap, class_weight, n_x)
         return part, task

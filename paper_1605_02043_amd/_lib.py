@@ -49,7 +49,9 @@ _SIGS = {
     "epk_partition": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, _I32P, _I32P, C.POINTER(Stats)]),
     "epk_partition_weighted": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, _I32P, _I32P, _I32P,
                                          C.POINTER(Stats)]),
+    "epk_partition_hub": (C.c_int, [C.POINTER(Graph), C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.POINTER(Stats)]),
     "epk_plan_create": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "epk_plan_create_hub": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, _I32P, C.c_int32, C.POINTER(_P)]),
     "epk_plan_create_weighted": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int32, C.c_int32, _I32P, C.POINTER(_P)]),
     "epk_plan_create_partitioned": (C.c_int, [C.POINTER(Graph), C.c_int32, C.c_int64, _I32P, _I32P, C.c_int32,
                                               C.POINTER(_P)]),

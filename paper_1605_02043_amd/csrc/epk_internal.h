@@ -59,9 +59,10 @@ void multilevel(int64_t m, int32_t cap, const std::vector<int32_t> &nbr, const s
                 std::vector<int32_t> &part, std::vector<int32_t> &task);
 void partition_stats(int32_t n, int64_t m, const int32_t *uv, int64_t k, const std::vector<int32_t> &part,
                      const std::vector<int32_t> &task, const Incidence &inc, epk_stats &st);
+// hub_degree > 0 (EP order only): the hub split (epk_partition_hub) before the multilevel partition.
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
                   std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out,
-                  const int32_t *class_weight = nullptr);
+                  const int32_t *class_weight = nullptr, int32_t hub_degree = 0);
 // A caller's partition: part_in[m] in [0, k); task_in[m] (may be NULL: parts
 // ascending, edge id inside a part) a permutation listing parts in order.
 // Capacity is not checked here (plan_build refuses parts above it).
@@ -207,7 +208,7 @@ inline bool fused_in_use(const epk_plan *p) {
 // given_task as for given_partition).
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status,
                      int64_t given_k = 0, const int32_t *given_part = nullptr, const int32_t *given_task = nullptr,
-                     const int32_t *class_weight = nullptr);
+                     const int32_t *class_weight = nullptr, int32_t hub_degree = 0);
 // Reduction records, one per replicated vertex: its packed id and its (at
 // most kRecSlots) slots, -1 past the last; a first slot of -1 sends the
 // vertex to the slot lists (more slots than a record holds).

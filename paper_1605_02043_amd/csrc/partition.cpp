@@ -219,10 +219,78 @@ void check_cancel() {
   if (tl_cancel && tl_cancel->load(std::memory_order_relaxed)) throw Cancelled{};
 }
 
+// The hub split: an edge whose class-y endpoint (the larger-degree one if both are in class y,
+// ties to the smaller id) has degree above hub_degree is a hub edge.  The hub edges, sorted by
+// (that endpoint, the other endpoint, edge id), fill parts 0 .. kh-1 in runs of cap; the other
+// edges, in ascending id, form a graph of their own that the multilevel partition splits into
+// parts kh, kh+1, ... .  Task order: the hub parts, then the multilevel task order.
+static void hub_split(const epk_graph *g, int32_t cap, int32_t hub_degree, const int32_t *class_weight,
+                      const Incidence &inc, std::vector<int32_t> &part, std::vector<int32_t> &task, int64_t &k) {
+  const int64_t m = g->n_edges;
+  const int32_t *uv = g->edge_uv;
+  auto deg = [&](int32_t v) { return inc.off[v + 1] - inc.off[v]; };
+  std::vector<int32_t> hub, rest;
+  std::vector<int32_t> key(size_t(m), -1);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = uv[2 * e], v = uv[2 * e + 1];
+    const bool yu = u >= g->n_x, yv = v >= g->n_x;
+    int32_t h = -1;
+    if (yu && yv)
+      h = (deg(u) > deg(v) || (deg(u) == deg(v) && u < v)) ? u : v;
+    else if (yu)
+      h = u;
+    else if (yv)
+      h = v;
+    if (h >= 0 && deg(h) > hub_degree) {
+      key[e] = h;
+      hub.push_back(int32_t(e));
+    } else {
+      rest.push_back(int32_t(e));
+    }
+  }
+  std::sort(hub.begin(), hub.end(), [&](int32_t a, int32_t b) {
+    const int32_t oa = uv[2 * a] == key[a] ? uv[2 * a + 1] : uv[2 * a];
+    const int32_t ob = uv[2 * b] == key[b] ? uv[2 * b + 1] : uv[2 * b];
+    if (key[a] != key[b]) return key[a] < key[b];
+    if (oa != ob) return oa < ob;
+    return a < b;
+  });
+  const int64_t nh = int64_t(hub.size()), kh = (nh + cap - 1) / cap;
+  part.assign(size_t(m), 0);
+  task.resize(size_t(m));
+  for (int64_t j = 0; j < nh; ++j) {
+    part[hub[j]] = int32_t(j / cap);
+    task[j] = hub[j];
+  }
+  k = kh;
+  const int64_t mr = int64_t(rest.size());
+  if (mr == 0) return;
+  std::vector<int32_t> uv_r(size_t(2 * mr));
+  for (int64_t j = 0; j < mr; ++j) {
+    uv_r[2 * j] = uv[2 * int64_t(rest[j])];
+    uv_r[2 * j + 1] = uv[2 * int64_t(rest[j]) + 1];
+  }
+  const epk_graph sub{g->n_vertices, g->n_x, mr, uv_r.data(), nullptr, 0};
+  Incidence inc_r;
+  build_incidence(sub.n_vertices, mr, sub.edge_uv, inc_r);
+  std::vector<int32_t> nbr, nbw, part_r, task_r;
+  const bool weighted = class_weight && (class_weight[0] != 1 || class_weight[1] != 1);
+  contracted_links(mr, sub.edge_uv, inc_r, nbr, weighted ? &nbw : nullptr, g->n_x, class_weight);
+  multilevel(mr, cap, nbr, weighted ? &nbw : nullptr, part_r, task_r);
+  for (int64_t j = 0; j < mr; ++j) {
+    part[rest[j]] = int32_t(kh + part_r[j]);
+    task[nh + j] = rest[task_r[j]];
+  }
+  k = kh + multilevel_parts(mr, cap);
+}
+
 int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<int32_t> &part,
-                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out, const int32_t *class_weight) {
+                  std::vector<int32_t> &task, epk_stats &st, Incidence *inc_out, const int32_t *class_weight,
+                  int32_t hub_degree) {
   if (cap < 1) return fail(EPK_EINVAL, "capacity must be >= 1");
   if (order < EPK_ORDER_EP || order > EPK_ORDER_GREEDY) return fail(EPK_EINVAL, "unknown order");
+  if (hub_degree < 0) return fail(EPK_EINVAL, "hub_degree must be >= 0");
+  if (hub_degree > 0 && order != EPK_ORDER_EP) return fail(EPK_EINVAL, "the hub split applies to the EP order only");
   if (class_weight) {
     for (int c = 0; c < 2; ++c)
       if (class_weight[c] < 1 || class_weight[c] > kMaxClassWeight)
@@ -243,6 +311,8 @@ int run_partition(const epk_graph *g, int32_t cap, int32_t order, std::vector<in
       random_order(m, cap, part, task);
     } else if (order == EPK_ORDER_GREEDY) {
       greedy_vertex_cut(g->n_vertices, m, g->edge_uv, cap, part, task);
+    } else if (hub_degree > 0) {
+      hub_split(g, cap, hub_degree, class_weight, inc, part, task, k);
     } else {
       std::vector<int32_t> nbr, nbw;
       const bool weighted = class_weight && (class_weight[0] != 1 || class_weight[1] != 1);
@@ -328,6 +398,25 @@ int epk_partition_weighted(const epk_graph *g, int32_t capacity, int32_t order, 
   std::vector<int32_t> part, task;
   epk_stats st;
   s = epk::run_partition(g, capacity, order, part, task, st, nullptr, class_weight);
+  if (s) return s;
+  if (g->n_edges > 0) {
+    std::memcpy(part_of_edge, part.data(), sizeof(int32_t) * size_t(g->n_edges));
+    if (task_order) std::memcpy(task_order, task.data(), sizeof(int32_t) * size_t(g->n_edges));
+  }
+  if (stats) *stats = st;
+  return EPK_OK;
+}
+
+int epk_partition_hub(const epk_graph *g, int32_t capacity, const int32_t *class_weight, int32_t hub_degree,
+                      int32_t *part_of_edge, int32_t *task_order, epk_stats *stats) {
+  epk::clear_error();
+  int s = epk::validate_graph(g, -1);
+  if (s) return s;
+  if (g->n_edges > 0 && !part_of_edge) return epk::fail(EPK_EINVAL, "part_of_edge is NULL");
+  if (hub_degree < 1) return epk::fail(EPK_EINVAL, "hub_degree must be >= 1");
+  std::vector<int32_t> part, task;
+  epk_stats st;
+  s = epk::run_partition(g, capacity, EPK_ORDER_EP, part, task, st, nullptr, class_weight, hub_degree);
   if (s) return s;
   if (g->n_edges > 0) {
     std::memcpy(part_of_edge, part.data(), sizeof(int32_t) * size_t(g->n_edges));

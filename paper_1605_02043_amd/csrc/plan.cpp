@@ -135,7 +135,8 @@ struct Build {
 }  // namespace
 
 epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kind, int *status, int64_t given_k,
-                     const int32_t *given_part, const int32_t *given_task, const int32_t *class_weight) {
+                     const int32_t *given_part, const int32_t *given_task, const int32_t *class_weight,
+                     int32_t hub_degree) {
   *status = EPK_OK;
   if (kind != EPK_FLUX5 && kind != EPK_SPMV) {
     *status = fail(EPK_EINVAL, "unknown kind");
@@ -167,7 +168,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->m = g->n_edges;
     P->wg = kind == EPK_SPMV ? std::max(64, ((cap + 63) / 64) * 64) : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
     Incidence inc;
-    int s = order >= 0 ? run_partition(g, cap, order, P->part, P->task, P->stats, &inc, class_weight)
+    int s = order >= 0 ? run_partition(g, cap, order, P->part, P->task, P->stats, &inc, class_weight, hub_degree)
                        : given_partition(g, given_k, given_part, given_task, P->part, P->task, P->stats, &inc);
     if (s) {
       delete P;
@@ -668,6 +669,19 @@ int epk_plan_create_weighted(const epk_graph *g, int32_t capacity, int32_t order
   *out = nullptr;
   int s = EPK_OK;
   epk_plan *p = epk::plan_build(g, capacity, order, kind, &s, 0, nullptr, nullptr, class_weight);
+  if (!p) return s ? s : epk::fail(EPK_EINVAL, "plan build failed");
+  *out = p;
+  return EPK_OK;
+}
+
+int epk_plan_create_hub(const epk_graph *g, int32_t capacity, int32_t kind, const int32_t *class_weight,
+                        int32_t hub_degree, epk_plan **out) {
+  epk::clear_error();
+  if (!out) return epk::fail(EPK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hub_degree < 1) return epk::fail(EPK_EINVAL, "hub_degree must be >= 1");
+  int s = EPK_OK;
+  epk_plan *p = epk::plan_build(g, capacity, EPK_ORDER_EP, kind, &s, 0, nullptr, nullptr, class_weight, hub_degree);
   if (!p) return s ? s : epk::fail(EPK_EINVAL, "plan build failed");
   *out = p;
   return EPK_OK;

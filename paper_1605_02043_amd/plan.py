@@ -40,17 +40,33 @@ def _class_weight(class_weight):
     return w
 
 
-def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep", class_weight=None, n_x: int = 0):
+def _hub_degree(order, hub_degree):
+    h = int(hub_degree)
+    if h < 0:
+        raise ValueError("hub_degree must be >= 0")
+    if h and order != "ep":
+        raise ValueError("the hub split applies to the EP order only")
+    return h
+
+
+def partition(edges: np.ndarray, n: int, cap: int, order: str = "ep", class_weight=None, n_x: int = 0,
+              hub_degree: int = 0):
     """Edge partition (host): returns (part[m], task_order[m], stats dict).  class_weight
-    (EP order): per-class vertex weights {x, y}, x being the vertices below n_x."""
+    (EP order): per-class vertex weights {x, y}, x being the vertices below n_x.  hub_degree > 0
+    (EP order): the hub split first (the edges of class-y vertices of higher degree in runs of
+    cap, in vertex order)."""
     gs, keep = make_graph(edges, n, None, n_x)
     m = gs.n_edges
     part = np.empty(m, dtype=np.int32)
     task = np.empty(m, dtype=np.int32)
     st = Stats()
     w = _class_weight(class_weight)
-    check(lib.epk_partition_weighted(C.byref(gs), int(cap), _lib.ORDER[order], i32p(w), i32p(part), i32p(task),
-                                     C.byref(st)))
+    h = _hub_degree(order, hub_degree)
+    if h:
+        check(lib.epk_partition_hub(C.byref(gs), int(cap), i32p(w), h, i32p(part), i32p(task), C.byref(st)))
+    else:
+        check(lib.epk_partition_weighted(C.byref(gs), int(cap), _lib.ORDER[order], i32p(w), i32p(part), i32p(task),
+                                         C.byref(st)))
     del keep
     return part, task, st.as_dict()
 
@@ -96,7 +112,7 @@ class Plan:
     """
 
     def __init__(self, edges, n: int, cap: int, geom, order: str = "ep", kind: str = "flux5", n_x: int = 0,
-                 class_weight=None):
+                 class_weight=None, hub_degree: int = 0):
         self.kind = kind
         self.n = int(n)
         self.n_x = int(n_x)
@@ -106,8 +122,12 @@ class Plan:
         gs, keep = make_graph(edges, n, geom, n_x)
         h = C.c_void_p()
         w = _class_weight(class_weight)
-        check(lib.epk_plan_create_weighted(C.byref(gs), int(cap), _lib.ORDER[order], _lib.KIND[kind], i32p(w),
-                                           C.byref(h)))
+        hd = _hub_degree(order, hub_degree)
+        if hd:
+            check(lib.epk_plan_create_hub(C.byref(gs), int(cap), _lib.KIND[kind], i32p(w), hd, C.byref(h)))
+        else:
+            check(lib.epk_plan_create_weighted(C.byref(gs), int(cap), _lib.ORDER[order], _lib.KIND[kind], i32p(w),
+                                               C.byref(h)))
         del keep
         self._h = h
         self.image = None

@@ -550,3 +550,50 @@ def test_weighted_partition_parity_and_errors():
     p3, t3 = P.part_of_edge()
     p4, t4 = multilevel.partition(g["edges"], g["n"], 128, class_weight=(1, 4), n_x=g["n_x"])[:2]
     assert np.array_equal(p3, p4) and np.array_equal(t3, t4)
+
+
+def test_hub_partition_parity_and_errors():
+    """The library's hub split equals the oracle's bit for bit: the hand-derived cases, random
+    power-law bipartite graphs with and without class weights, a small R-MAT, one-class graphs;
+    the plan built with it carries the same partition; bad arguments are refused."""
+    from oracle import hub
+
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hub_split7.json")))
+    for c in G["cases"]:
+        p, t, st_ = partition(np.array(c["edges"]), c["n"], c["cap"], "ep", None, c["n_x"], c["hub_degree"])
+        assert p.tolist() == c["part"] and t.tolist() == c["task"] and st_["n_parts"] == c["n_parts"]
+    rng = np.random.default_rng(5)
+    for trial in range(30):
+        n_x, n_y = int(rng.integers(2, 50)), int(rng.integers(2, 50))
+        m = int(rng.integers(1, 800))
+        cap = int(rng.integers(1, 48))
+        hd = int(rng.integers(1, 40))
+        cw = None if trial % 2 else (1, int(rng.integers(1, 9)))
+        py = 1.0 / np.arange(1, n_y + 1) ** 1.2
+        E = np.stack([rng.integers(0, n_x, m), n_x + rng.choice(n_y, size=m, p=py / py.sum())], 1).astype(np.int32)
+        p1, t1, st1 = partition(E, n_x + n_y, cap, "ep", cw, n_x, hd)
+        p2, t2, k2 = hub.partition(E, n_x + n_y, cap, hd, cw, n_x)
+        assert np.array_equal(p1, p2) and np.array_equal(t1, t2) and st1["n_parts"] == k2, trial
+        assert st1["max_part_edges"] <= cap
+        c = cost.partition_cost(E, n_x + n_y, p2, k2)
+        assert st1["loads"] == c["loads"] and st1["cost"] == c["cost"]
+    for trial in range(10):  # one class: keys by degree
+        n, m = int(rng.integers(3, 40)), int(rng.integers(1, 300))
+        E = rng.integers(0, n, size=(m, 2)).astype(np.int32)
+        E = E[E[:, 0] != E[:, 1]]
+        cap, hd = int(rng.integers(1, 30)), int(rng.integers(1, 12))
+        p1, t1, _ = partition(E, n, cap, "ep", None, 0, hd)
+        p2, t2, _ = hub.partition(E, n, cap, hd, None, 0)
+        assert np.array_equal(p1, p2) and np.array_equal(t1, t2), trial
+    g = spmv_graph(gen.rmat(scale=10, n_edges=8000, seed=6), np.arange(8000))
+    P = Plan(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"], class_weight=(1, 4), hub_degree=16)
+    p3, t3 = P.part_of_edge()
+    p4, t4, _ = hub.partition(g["edges"], g["n"], 128, 16, (1, 4), g["n_x"])
+    assert np.array_equal(p3, p4) and np.array_equal(t3, t4)
+    gs, keep = make_graph(E, n, None, 0)
+    part = np.empty(len(E), np.int32)
+    assert _lib.lib.epk_partition_hub(C.byref(gs), 4, None, 0, _lib.i32p(part), None, None) == _lib.EPK_EINVAL
+    with pytest.raises(ValueError):
+        partition(E, n, 4, "ggp", None, 0, 3)
+    with pytest.raises(ValueError):
+        Plan(g["edges"], g["n"], 128, g["w"], kind="spmv", n_x=g["n_x"], order="input", hub_degree=4)

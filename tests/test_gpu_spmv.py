@@ -18,11 +18,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run(g, cap, order, x, class_weight=None):
+def _run(g, cap, order, x, class_weight=None, hub_degree=0):
     from paper_1605_02043_amd import Plan
 
     P = Plan(g["edges"], g["n"], cap, g["w"], order=order, kind="spmv", n_x=g["n_x"],
-             class_weight=class_weight).upload("cuda")
+             class_weight=class_weight, hub_degree=hub_degree).upload("cuda")
     perm = P.perm()
     n_x = g["n_x"]
     xp = torch.from_numpy(np.ascontiguousarray(x[perm[:n_x]])).cuda()
@@ -46,17 +46,18 @@ def test_spmv_rmat_small(order, cap):
     assert_close(f"spmv14/{order}/{cap}", y, ref, A)
 
 
-@pytest.mark.parametrize("cap", [256, 1024])
-def test_spmv_rmat_weighted_partition(cap):
-    """EP with y copies weighing 4 (the partition cuts x chains before y chains): the same
-    kernels on a plan with few replicated y, forward and adjoint against the oracle."""
+@pytest.mark.parametrize("cap,hub", [(256, 0), (1024, 0), (256, 16), (1024, 64)])
+def test_spmv_rmat_weighted_partition(cap, hub):
+    """EP with y copies weighing 4 (the partition cuts x chains before y chains), alone and after
+    the hub split (the rows above `hub` nonzeros in runs of cap): the same kernels on plans
+    with few replicated y, forward and adjoint against the oracle."""
     R = gen.rmat(scale=14, n_edges=1 << 18, seed=2)
     g = spmv_graph(R, R["shuffle"])
-    say(f"case spmv scale14 weighted cap={cap}")
-    y, P = _run(g, cap, "ep", R["x"], class_weight=(1, 4))
+    say(f"case spmv scale14 weighted cap={cap} hub={hub}")
+    y, P = _run(g, cap, "ep", R["x"], class_weight=(1, 4), hub_degree=hub)
     ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
     A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
-    assert_close(f"spmv14/weighted/{cap}", y, ref, A)
+    assert_close(f"spmv14/weighted/{cap}/{hub}", y, ref, A)
     perm = P.perm()
     n_x = g["n_x"]
     gy = np.random.default_rng(3).standard_normal(g["n"] - n_x).astype(np.float32)
@@ -67,25 +68,26 @@ def test_spmv_rmat_weighted_partition(cap):
     out[perm[:n_x]] = gx.cpu().numpy()
     gref = spmv.backward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)[0]
     gA = spmv.backward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)[0]
-    assert_close(f"spmv14/weighted/{cap}/adjoint", out, gref, gA)
+    assert_close(f"spmv14/weighted/{cap}/{hub}/adjoint", out, gref, gA)
 
 
-def test_spmv_rmat_full_size_three_orders():
+def test_spmv_rmat_full_size_orders():
     R = gen.rmat(scale=20, n_edges=1 << 24, seed=0)
     say("case spmv rmat20 full size")
     orders = {
-        "shuffled-ep": (R["shuffle"], "ep"),
-        "shuffled": (R["shuffle"], "input"),
-        "row-sorted": (np.argsort(R["rows"], kind="stable"), "input"),
+        "shuffled-ep": (R["shuffle"], "ep", None, 0),
+        "shuffled-ep-hub16": (R["shuffle"], "ep", (1, 4), 16),
+        "shuffled": (R["shuffle"], "input", None, 0),
+        "row-sorted": (np.argsort(R["rows"], kind="stable"), "input", None, 0),
     }
     ref = A = None
-    for name, (perm_e, order) in orders.items():
+    for name, (perm_e, order, cw, hub) in orders.items():
         g = spmv_graph(R, perm_e)
         if ref is None:
             ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
             A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
         say(f"case spmv rmat20 {name}")
-        y, P = _run(g, 256, order, R["x"])
+        y, P = _run(g, 256, order, R["x"], class_weight=cw, hub_degree=hub)
         assert_close(f"spmv20/{name}", y, ref, A)
         if name == "shuffled-ep":
             st = P.stats

@@ -651,3 +651,70 @@ def test_weighted_multilevel_not_below_brute_force(seed):
     part, _, k = multilevel.partition(E, n_x + n_y, cap, class_weight=(1, 5), n_x=n_x)
     best, _ = brute.min_edge_partition_cost(E, n_x + n_y, cap, w)
     assert cost.weighted_cost(E, n_x + n_y, part, w) >= best
+
+
+# ------------------------------------------------------------------ the hub split (an extension)
+
+from oracle import hub  # noqa: E402
+
+
+def test_hub_split_hand_derived(golden_dir):
+    """Both hand-derived cases: the bipartite one pins the sort by the other endpoint and the
+    run of cap; the one-class one pins the key rule (larger degree, ties to the smaller id, an
+    edge listed high id first) and the EP part of the rest following the hub parts."""
+    G = json.load(open(os.path.join(golden_dir, "hub_split7.json")))
+    for c in G["cases"]:
+        part, task, k = hub.partition(c["edges"], c["n"], c["cap"], c["hub_degree"], None, c["n_x"])
+        assert part.tolist() == c["part"], c["name"]
+        assert task.tolist() == c["task"], c["name"]
+        assert k == c["n_parts"], c["name"]
+
+
+def _bipartite_power_law(rng, n_x, n_y, m, alpha=1.2):
+    """Edges (x, n_x + y) with y drawn from a Zipf-like law, so that a few y have high degree."""
+    py = 1.0 / np.arange(1, n_y + 1) ** alpha
+    y = rng.choice(n_y, size=m, p=py / py.sum())
+    x = rng.integers(0, n_x, m)
+    return np.stack([x, n_x + y], 1).astype(np.int64)
+
+
+@settings(max_examples=25, deadline=None)
+@given(st.integers(2, 40), st.integers(2, 40), st.integers(1, 400), st.integers(1, 40), st.integers(1, 30),
+       st.integers(0, 10_000))
+def test_hub_split_invariants(n_x, n_y, m, cap, hd, seed):
+    """Every edge in exactly one part, parts within the capacity and listed in ascending order by
+    the task order; the hub parts hold exactly the hub edges, in (key, other, id) order; a hub
+    of degree d spans at most ceil(d/cap) + 1 parts."""
+    rng = np.random.default_rng(seed)
+    E = _bipartite_power_law(rng, n_x, n_y, m)
+    n = n_x + n_y
+    part, task, k = hub.partition(E, n, cap, hd, None, n_x)
+    assert sorted(task.tolist()) == list(range(m))
+    assert (np.diff(part[task]) >= 0).all()
+    counts = np.bincount(part, minlength=k)
+    assert len(counts) == k and counts.max() <= cap
+    deg = np.bincount(E.ravel(), minlength=n)
+    is_hub = deg[E[:, 1]] > hd
+    nh = int(is_hub.sum())
+    kh = -(-nh // cap)
+    assert (part[is_hub] < kh).all() and (part[~is_hub] >= kh).all()
+    order = sorted(np.flatnonzero(is_hub).tolist(), key=lambda e: (E[e, 1], E[e, 0], e))
+    assert task[:nh].tolist() == order
+    for v in np.unique(E[is_hub, 1]):
+        spans = len(np.unique(part[E[:, 1] == v]))
+        assert spans <= -(-deg[v] // cap) + 1
+
+
+@settings(max_examples=20, deadline=None)
+@given(st.integers(2, 30), st.integers(0, 200), st.integers(1, 30), st.integers(0, 10_000))
+def test_hub_split_without_hubs_is_the_ep_order(n, m, cap, seed):
+    """With hub_degree at or above every degree the split finds no hub edge and the result is the
+    plain EP order (weighted and unweighted, one class and two)."""
+    rng = np.random.default_rng(seed)
+    E = rng.integers(0, n, size=(m, 2))
+    E = E[E[:, 0] != E[:, 1]]
+    deg_max = int(np.bincount(E.ravel(), minlength=n).max()) if len(E) else 0
+    for n_x, cw in ((0, None), (n // 2, (1, 3))):
+        p1, t1, k1 = hub.partition(E, n, cap, max(deg_max, 1), cw, n_x)
+        p2, t2, k2 = multilevel.partition(E, n, cap, cw, n_x)
+        assert np.array_equal(p1, p2) and np.array_equal(t1, t2) and k1 == k2
