@@ -104,6 +104,35 @@ def summarize_trace(path: str) -> str:
     return "\n".join(out)
 
 
+def summarize_spmv_trace(path: str) -> str:
+    """Markdown summary of a rocprofv3 kernel trace (CSV) of `bench.py --workload rmat20`, per task
+    order: the orders run one after another, each after its own partition and plan build, so the
+    library's dispatches split at the len(SPMV_ORDERS) - 1 longest gaps between them."""
+    import csv
+
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if "epk::" in r["Kernel_Name"]:
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short_name(r["Kernel_Name"]),
+                             int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)))
+    rows.sort()
+    gaps = sorted(range(len(rows) - 1), key=lambda i: rows[i][1] - rows[i + 1][0])[:len(SPMV_ORDERS) - 1]
+    cuts = [0] + sorted(i + 1 for i in gaps) + [len(rows)]
+    out = ["| order | kernel | workgroups | launches | mean us | median us |", "|---|---|---|---|---|---|"]
+    for order, a, b in zip(SPMV_ORDERS, cuts[:-1], cuts[1:]):
+        groups = {}
+        for t0, t1, name, grid in rows[a:b]:
+            groups.setdefault((name, grid), []).append((t1 - t0) / 1e3)
+        for (name, grid), d in sorted(groups.items(), key=lambda kv: -len(kv[1])):
+            out.append(f"| {order} | {name} | {grid} | {len(d)} | {np.mean(d):.2f} | {np.median(d):.2f} |")
+    shortest = min(rows[i + 1][0] - rows[i][1] for i in gaps) / 1e9 if gaps else 0.0
+    out.append("")
+    out.append(f"(order boundaries: the {len(gaps)} longest gaps between library dispatches, the shortest of them "
+               f"{shortest:.2f} s)")
+    return "\n".join(out)
+
+
 def summarize_counters(paths) -> str:
     """Markdown summary of rocprofv3 counter collections (CSV) of bench.py: per kernel and grid
     size, the mean value of every counter per dispatch (counters accumulate over the device's
@@ -300,6 +329,8 @@ def _args():
                     help="print a markdown summary of a rocprofv3 kernel trace of this script and exit (no GPU)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print a markdown summary of rocprofv3 counter collections of this script and exit (no GPU)")
+    ap.add_argument("--summarize-spmv-trace", metavar="CSV",
+                    help="print the per-order markdown summary of a rmat20 kernel trace and exit (no GPU)")
     ap.add_argument("--spmv-traffic-json", nargs="+", metavar="CSV",
                     help="print the per-order SpMV traffic JSON from rmat20 counter CSVs and exit (no GPU)")
     ap.add_argument("--traffic-json", nargs="+", metavar=("WORKLOAD", "CSV"),
@@ -683,6 +714,9 @@ def main():
         return
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters))
+        return
+    if args.summarize_spmv_trace:
+        print(summarize_spmv_trace(args.summarize_spmv_trace))
         return
     if args.spmv_traffic_json:
         print(json.dumps(spmv_traffic_json(args.spmv_traffic_json), indent=1))
