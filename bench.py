@@ -2,14 +2,17 @@
 
 Workload (default): the 3D tetrahedral-mesh dual graph of a Kuhn 55^3 box,
 n = 998,250 cells, m = 1,978,350 interior faces, 5 float32 states per cell,
-face normal + area per edge, capacity 256, loss = sum r^2 (upstream gradient
-2r).  One step = forward (part kernel + reduction) then adjoint (part kernel
-+ reduction) over the whole mesh, inputs resident in HBM.  The partitioned
-(EP) order gives `value`; the default (cell-major input) order is timed the
-same way alongside.
+face normal + area per edge, capacity 256, loss L = 1/2 sum r^2 (so the
+adjoint's upstream gradient is r).  One step = forward (part kernel +
+reduction) then adjoint (part kernel + reduction) over the whole mesh, inputs
+resident in HBM.  The partitioned (EP) order gives `value`; the default
+(cell-major input) order is timed the same way alongside, as the paper
+compares its orders (Section 5.2, with memory transactions per order in
+Figures 10 and 14; here the L2-miss bytes of rocprofv3's request counters).
 
-Prints one JSON line.  Per-kernel durations come from HIP events recorded on
-the launch stream around every kernel of the timed steps.
+Prints one JSON line.  Step time: the timed steps captured in one HIP graph
+and replayed.  Kernel durations: each kernel's own dispatch timestamps
+(epk_run_stage_timed), warm and after a read-only 1 GiB cache scrub.
 """
 
 from __future__ import annotations
