@@ -35,7 +35,7 @@ DevPlan dev_plan(const epk_plan *p) {
   P.inc = dptr<uint16_t>(b, L.inc);
   P.loff = dptr<uint16_t>(b, L.loff);
   P.fid = dptr<int32_t>(b, L.fid);
-  P.pfid = p->kind == EPK_FLUX5 ? dptr<int32_t>(b, L.pfid) : nullptr;
+  P.pfid = dptr<int32_t>(b, L.pfid);
   P.rvid = dptr<int32_t>(b, L.rvid);
   P.roff = dptr<int32_t>(b, L.roff);
   P.sidx = p->vmajor ? dptr<int32_t>(b, L.sidx) : nullptr;

@@ -1281,38 +1281,40 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
 // ------------------------------------------------------------------ SpMV
 
 // LDS: xs[max_ux] | ys[max_uy] | ysl[max_uy] (slots of the foreign y) |
-// per-wave carry keys and values.
+// xid[max_nf] (foreign x ids) | per-wave carry keys and values.
 __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__restrict__ x, float *__restrict__ y,
                                                     float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
   const int part = part_of_block(blockIdx.x, P.k, swizzle);
   if (part >= P.k) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
-  const int4 ha = h4[0], hb = h4[1];
-  const int xo = ha.x, xn = ha.y, xf0 = ha.z, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
-  const int64_t e0 = P.eoff[part];
-  const int ne = int(P.eoff[part + 1] - e0);
   float *xs = smem;
   float *ys = xs + P.max_u;
   int32_t *ysl = reinterpret_cast<int32_t *>(ys + P.max_uy);
-  int *tkey = ysl + P.max_uy;
+  int32_t *xid = ysl + P.max_uy;
+  int *tkey = xid + P.max_nf;
   float *tval = reinterpret_cast<float *>(tkey + (nt >> 6));
   const int lane = tid & 63, wave = tid >> 6;
 
-  // batch 1: owned x block, foreign x ids (into the slots their values will
-  // take) and edge data; batch 2: foreign x values, each lane overwriting the id
-  // it read
-  int32_t *xid = reinterpret_cast<int32_t *>(xs + xn);
-  dma_block(xs, x + xo, xn, tid, nt);
-  dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.fid + xf0), xnf, tid, nt);
-  if (P.sidx) dma_block(reinterpret_cast<float *>(ysl), reinterpret_cast<const float *>(P.sidx + yf0), ynf, tid, nt);
-  const bool valid = tid < ne;
-  const int64_t ec = clamp_edge(P, int(e0), ne, tid);
+  // batch 1, all addressed from the part index: header, edge count, foreign x
+  // ids (fixed-stride copy) and edge records (part p's at p cap, zero past its
+  // count; lanes past the capacity re-read the last record)
+  const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
+  const int4 ha = h4[0], hb = h4[1];
+  const int ne = int(P.eoff[part + 1] - P.eoff[part]);
+  dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
+            P.max_nf, tid, nt);
+  const int64_t e0 = int64_t(part) * P.cap;
+  const int64_t ec = e0 + min(tid, P.cap - 1);
   const uint32_t w = P.eloc[ec];
   const float wt = P.geom[ec];
-  const uint32_t w_next = P.eloc[clamp_edge(P, int(e0), ne, tid + 1)];
+  const uint32_t w_next = P.eloc[e0 + min(tid + 1, P.cap - 1)];
   wait_staged();
+  const int xo = ha.x, xn = ha.y, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
+  const bool valid = tid < ne;
+  // batch 2: owned x block, foreign x values by id, slot indices of the foreign y
+  dma_block(xs, x + xo, xn, tid, nt);
+  if (P.sidx) dma_block(reinterpret_cast<float *>(ysl), reinterpret_cast<const float *>(P.sidx + yf0), ynf, tid, nt);
   for (int d = tid; d < xnf; d += nt) __builtin_amdgcn_global_load_lds(x + xid[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
   wait_staged();
 
@@ -1369,8 +1371,8 @@ __global__ void __launch_bounds__(1024) spmv_adj_kernel(DevPlan P, const float *
   const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
   const int4 ha = h4[0], hb = h4[1];
   const int xo = ha.x, xn = ha.y, xf0 = ha.z, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
-  const int64_t e0 = P.eoff[part];
-  const int ne = int(P.eoff[part + 1] - e0);
+  const int64_t e0 = int64_t(part) * P.cap;  // the part's record block
+  const int ne = int(P.eoff[part + 1] - P.eoff[part]);
   const int ux = xn + xnf;
   float *gys = smem;
   float *xs = gys + P.max_uy;

@@ -94,8 +94,8 @@ int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap) {
   const int64_t b = 4 * (max_uy + max_ux + cap) + 2 * (ncap + nlo) + 4 * max_ux;
   return (b + 15) & ~int64_t(15);
 }
-int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg) {
-  const int64_t b = 4 * (max_ux + 2 * max_uy) + 8 * (wg / 64);
+int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg, int64_t max_nf) {
+  const int64_t b = 4 * (max_ux + 2 * max_uy + max_nf) + 8 * (wg / 64);
   return (b + 15) & ~int64_t(15);
 }
 
@@ -241,10 +241,15 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->foreign_ids.clear();
     P->foreign_ids.reserve(size_t(P->stats.cost));
     std::vector<int32_t> stamp(size_t(n), -1), loc(size_t(n), 0);
-    // FLUX5 edge records sit at a fixed stride: part p's at [p cap, p cap + ne),
-    // the rest of its block zero.  A kernel then knows where a part's edges are
-    // before its header has arrived.  SpMV records are contiguous.
-    const int64_t me = kind == EPK_FLUX5 ? k * int64_t(cap) : m;
+    // Edge records sit at a fixed stride: part p's at [p cap, p cap + ne), the
+    // rest of its block zero.  A kernel then knows where a part's edges are
+    // before its header has arrived.
+    const int64_t me = k * int64_t(cap);
+    if (me >= (int64_t(1) << 31)) {
+      delete P;
+      *status = fail(EPK_ERANGE, "parts x capacity must be < 2^31 (32-bit edge offsets)");
+      return nullptr;
+    }
     P->me = me;
     std::vector<uint32_t> eloc(static_cast<size_t>(me));
     // 3D flux geometry (n, a) is stored as the area vector A = a n: 3 floats per edge
@@ -268,9 +273,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     std::vector<int32_t> xlofs;
     std::vector<int32_t> eid;  // SpMV adjoint: original edge id of each kernel-order edge
     if (kind == EPK_SPMV) {
-      xinc.resize(size_t(2 * m));  // a part's list starts at 2 e0, an even index
+      xinc.resize(size_t(2 * me));  // a part's list starts at 2 e0, an even index
       xlofs.reserve(size_t(k));
-      eid.resize(size_t(m));
+      eid.resize(size_t(me));
     }
     int64_t lofs = 0;
     int64_t fdev = 0;           // running x/all foreign offset in fid
@@ -354,6 +359,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
         red_foreign.insert(red_foreign.end(), fl[0].begin(), fl[0].end());
         fred += nf[0];
       } else {
+        const int64_t e0 = p * int64_t(cap);  // the part's record block
         // edges of the part sorted by local y (stable in task order)
         order_idx.resize(size_t(ne));
         std::vector<uint32_t> ly(static_cast<size_t>(ne)), lx(static_cast<size_t>(ne));
@@ -399,15 +405,14 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->max_u = max_u[0];
     P->max_uy = max_u[1];
     P->max_nf = max_nf;
-    // FLUX5: every part's foreign ids again, in a block of max_nf at p max_nf
-    // (padding -1 is never used), so a part's ids are found from its index alone
-    std::vector<int32_t> pfid;
-    if (kind == EPK_FLUX5) {
-      pfid.assign(size_t(k * max_nf), -1);
-      for (int64_t p = 0; p < k; ++p) {
-        const int32_t *h = &hdr[size_t(p) * kHdrInts];
-        std::copy(fid.begin() + h[4], fid.begin() + h[4] + h[5], pfid.begin() + p * max_nf);
-      }
+    // every part's foreign ids again (SpMV: its foreign x), in a block of max_nf
+    // at p max_nf (padding -1 is never used), so a part's ids are found from its
+    // index alone
+    std::vector<int32_t> pfid(size_t(k * max_nf), -1);
+    for (int64_t p = 0; p < k; ++p) {
+      const int32_t *h = &hdr[size_t(p) * kHdrInts];
+      const int32_t f0 = kind == EPK_FLUX5 ? h[4] : h[2], nf = kind == EPK_FLUX5 ? h[5] : h[3];
+      std::copy(fid.begin() + f0, fid.begin() + f0 + nf, pfid.begin() + p * max_nf);
     }
 
     // ---- reduction tables: for each replicated vertex of the reduced class,
@@ -618,7 +623,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
       P->bytes_reduce = 4 * R + 4 * (R + 1) + 20 * Cred + 40 * R + 20 * (nred - na);
       P->bytes_reduce_qnew = P->bytes_reduce + 40 * R + 40 * (nred - na);
     } else {
-      P->lds_fwd = spmv_lds(P->max_u, P->max_uy, P->wg);
+      P->lds_fwd = spmv_lds(P->max_u, P->max_uy, P->wg, P->max_nf);
       P->lds_bwd = spmv_adj_lds(P->max_u, P->max_uy, cap);
       // x loads = owned x + foreign x over all parts
       int64_t Lxs = 0, Cx = 0;
@@ -793,7 +798,7 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   if (xcd_swizzle < -1 || xcd_swizzle > 1) return epk::fail(EPK_EINVAL, "xcd_swizzle must be -1, 0 or 1");
   if (wg != 0) {
     p->wg = wg;
-    if (p->kind == EPK_SPMV) p->lds_fwd = epk::spmv_lds(p->max_u, p->max_uy, wg);
+    if (p->kind == EPK_SPMV) p->lds_fwd = epk::spmv_lds(p->max_u, p->max_uy, wg, p->max_nf);
   }
   if (xcd_swizzle >= 0) p->swizzle = xcd_swizzle;
   p->pipe = 0;  // the pipelined grid depends on both: set it again
