@@ -202,7 +202,10 @@ int epk_plan_stats(const epk_plan *p, epk_stats *s);
  * use; with the single launch, [7] / [8] hold the whole pass.             */
 int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
- * 64; SPMV requires wg >= capacity; 0 keeps the current one) and
+ * 64; FLUX5 requires capacity <= 8 wg, SPMV capacity <= 4 wg: each
+ * lane then takes ceil(capacity / wg) consecutive edges of its part (the
+ * SpMV default is two; the SpMV adjoint always runs one edge per lane);
+ * 0 keeps the current one) and
  * xcd_swizzle (1: XCD x runs the consecutive parts [x*ceil(k/8),
  * (x+1)*ceil(k/8)), so parts sharing vertices share an L2; 0: part =
  * workgroup id; -1 keeps the current one).  Host only.                   */
@@ -222,9 +225,10 @@ int epk_plan_set_pipeline(epk_plan *p, int32_t blocks_per_cu);
  * 0 part-major (each part writes its foreign partials as one block and the
  * reduction gathers a vertex's partials through a slot list), 1 vertex-major
  * (each part scatters its partials so that a vertex's partials sit side by
- * side and the reduction reads them as one run), -1 automatic (vertex-major
- * when the reduced class has more than four partials per replicated vertex,
- * as around power-law hubs).  The sum order, ascending part id, and hence
+ * side and the reduction reads them as one run), -1 automatic (FLUX5:
+ * vertex-major when the reduced class has more than four partials per
+ * replicated vertex; SPMV: vertex-major while the partials number at most
+ * one per eight edges, part-major above).  The sum order, ascending part id, and hence
  * every result bit, is the same under both.  Host only; takes effect at the
  * next launch.  The vertex-major layout also stages each part's slot
  * indices in LDS: EPK_ERANGE (layout unchanged) if they no longer fit.   */

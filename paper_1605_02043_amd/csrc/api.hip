@@ -688,7 +688,8 @@ int epk_spmv_adjoint(const epk_plan *p, const float *x, const float *g_y, float 
   const DevPlan P = dev_plan(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   float *ws = static_cast<float *>(d_ws);
-  hipError_t e = launch_spmv_adjoint(P, p->wg, size_t(p->lds_bwd), x, g_y, g_x, g_w, ws, p->swizzle, s);
+  const int wg_adj = std::max(64, ((p->cap + 63) / 64) * 64);  // one edge per lane
+  hipError_t e = launch_spmv_adjoint(P, wg_adj, size_t(p->lds_bwd), x, g_y, g_x, g_w, ws, p->swizzle, s);
   if (e != hipSuccess) return hip_status(e, "adjoint kernel launch");
   return hip_status(launch_reduce(dev_plan_xreduce(p), 1, g_x, ws, nullptr, nullptr, 0.f, s), "reduce launch");
 }

@@ -195,6 +195,7 @@ int64_t flux_pipe_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool
 int64_t flux_cached_lds(int64_t max_u, int64_t max_nf, int64_t cap, bool bwd, bool sidx);
 void set_flux_lds(epk_plan *p);  // all of a FLUX5 plan's LDS sizes for its current layout
 int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg, int64_t max_nf);
+bool auto_vmajor(const epk_plan *p);
 int64_t spmv_adj_lds(int64_t max_ux, int64_t max_uy, int64_t cap);
 int64_t plan_bytes(const epk_plan *p, int which);
 // The single-launch reduction applies to FLUX5 plans that allow it (part-major workspace, no vertex

@@ -1282,6 +1282,8 @@ __global__ void __launch_bounds__(256) flux_bwd_pipe(DevPlan P, const float *__r
 
 // LDS: xs[max_ux] | ys[max_uy] | ysl[max_uy] (slots of the foreign y) |
 // xid[max_nf] (foreign x ids) | per-wave carry keys and values.
+// EPT consecutive edges per lane (EPT * blockDim.x >= cap).
+template <int EPT>
 __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__restrict__ x, float *__restrict__ y,
                                                     float *__restrict__ ws, int swizzle) {
   extern __shared__ float smem[];
@@ -1298,51 +1300,78 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
 
   // batch 1, all addressed from the part index: header, edge count, foreign x
   // ids (fixed-stride copy) and edge records (part p's at p cap, zero past its
-  // count; lanes past the capacity re-read the last record)
+  // count; positions past the capacity re-read the last record)
   const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
   const int4 ha = h4[0], hb = h4[1];
   const int ne = int(P.eoff[part + 1] - P.eoff[part]);
   dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
             P.max_nf, tid, nt);
-  const int64_t e0 = int64_t(part) * P.cap;
-  const int64_t ec = e0 + min(tid, P.cap - 1);
-  const uint32_t w = P.eloc[ec];
-  const float wt = P.geom[ec];
-  const uint32_t w_next = P.eloc[e0 + min(tid + 1, P.cap - 1)];
+  const uint32_t *el = P.eloc + int64_t(part) * P.cap;
+  const float *eg = P.geom + int64_t(part) * P.cap;
+  const int j0 = tid * EPT;
+  uint32_t w[EPT];
+  float wt[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int j = min(j0 + i, P.cap - 1);
+    w[i] = el[j];
+    wt[i] = eg[j];
+  }
+  const uint32_t w_next = el[min(j0 + EPT, P.cap - 1)];
   wait_staged();
   const int xo = ha.x, xn = ha.y, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
-  const bool valid = tid < ne;
   // batch 2: owned x block, foreign x values by id, slot indices of the foreign y
   dma_block(xs, x + xo, xn, tid, nt);
   if (P.sidx) dma_block(reinterpret_cast<float *>(ysl), reinterpret_cast<const float *>(P.sidx + yf0), ynf, tid, nt);
   for (int d = tid; d < xnf; d += nt) __builtin_amdgcn_global_load_lds(x + xid[d], EPK_LDS(xs + xn + (d - lane)), 4, 0, 0);
   wait_staged();
 
-  // one edge per thread, edges sorted by local y: inclusive segmented scan per wavefront
-  const int key = valid ? int(w >> 16) : 0x7fffffff;
-  float v = valid ? wt * xs[w & 0xffffu] : 0.0f;
+  // edges sorted by local y: the lane's EPT edges summed run by run, then an
+  // inclusive segmented scan of the lanes' last runs per wavefront
+  int k[EPT];
+  float sv[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const bool ok = j0 + i < ne;
+    k[i] = ok ? int(w[i] >> 16) : 0x7fffffff;
+    const float v = ok ? wt[i] * xs[w[i] & 0xffffu] : 0.0f;
+    sv[i] = (i > 0 && k[i] == k[i - 1]) ? sv[i - 1] + v : v;
+  }
+  const int key = k[EPT - 1];
+  float v = sv[EPT - 1];
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const float vu = __shfl_up(v, d, 64);
     const int ku = __shfl_up(key, d, 64);
     if (lane >= d && ku == key) v = vu + v;
   }
-  int key_next = __shfl_down(key, 1, 64);
-  if (lane == 63) key_next = (tid + 1 < ne) ? int(w_next >> 16) : 0x7ffffffe;
+  // the earlier lanes' sum of this lane's first key (runs that start at its first edge)
+  const float vp = __shfl_up(v, 1, 64);
+  const int kp = __shfl_up(key, 1, 64);
+  const bool carry_in = lane > 0 && kp == k[0];
+  int key_next = __shfl_down(k[0], 1, 64);
+  if (lane == 63) key_next = (j0 + EPT < ne) ? int(w_next >> 16) : 0x7ffffffe;
+  const bool last_ok = j0 + EPT - 1 < ne;
   if (lane == 63) {
-    tkey[wave] = (valid && key_next == key) ? key : -1;
+    tkey[wave] = (last_ok && key_next == key) ? key : -1;
     tval[wave] = v;
   }
   __syncthreads();
-  if (valid && key_next != key) {  // end of a segment: add the carries of earlier wavefronts
+  // ends of segments: add the carries of earlier wavefronts
+  auto finish = [&](int kk, float t) {
     float carry = 0.0f;
     bool has = false;
-    for (int wp = wave - 1; wp >= 0 && tkey[wp] == key; --wp) {
+    for (int wp = wave - 1; wp >= 0 && tkey[wp] == kk; --wp) {
       carry = has ? carry + tval[wp] : tval[wp];
       has = true;
     }
-    ys[key] = has ? carry + v : v;
+    ys[kk] = has ? carry + t : t;
+  };
+#pragma unroll
+  for (int i = 0; i < EPT - 1; ++i) {
+    if (j0 + i < ne && k[i + 1] != k[i]) finish(k[i], (carry_in && k[i] == k[0]) ? vp + sv[i] : sv[i]);
   }
+  if (last_ok && key_next != key) finish(key, v);
   __syncthreads();
   for (int d = tid; d < yn; d += nt) y[yo + d] = ys[d];
   if (P.sidx) {
@@ -1636,7 +1665,16 @@ hipError_t launch_flux_pipe(const DevPlan &P, int wg, int grid, size_t lds, cons
 hipError_t launch_spmv(const DevPlan &P, int wg, size_t lds, const float *x, float *y, float *ws, int swizzle,
                        hipStream_t s) {
   if (P.k == 0) return hipSuccess;
-  EPK_LAUNCH(spmv_kernel, dim3(grid_of_parts(P.k, swizzle)), dim3(wg), lds, s, P, x, y, ws, swizzle);
+  const dim3 grid(grid_of_parts(P.k, swizzle)), block(wg);
+  const int ept = (P.cap + wg - 1) / wg;
+  if (ept <= 1)
+    EPK_LAUNCH((spmv_kernel<1>), grid, block, lds, s, P, x, y, ws, swizzle);
+  else if (ept == 2)
+    EPK_LAUNCH((spmv_kernel<2>), grid, block, lds, s, P, x, y, ws, swizzle);
+  else if (ept <= 4)
+    EPK_LAUNCH((spmv_kernel<4>), grid, block, lds, s, P, x, y, ws, swizzle);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

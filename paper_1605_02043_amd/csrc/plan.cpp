@@ -99,6 +99,16 @@ int64_t spmv_lds(int64_t max_ux, int64_t max_uy, int64_t wg, int64_t max_nf) {
   return (b + 15) & ~int64_t(15);
 }
 
+// The automatic workspace layout.  FLUX5: vertex-major when the reduction
+// gathers many partials per replicated vertex (more than four).  SpMV (4-byte
+// partials): vertex-major while the part kernel's scattered partial writes
+// stay few (at most one per eight edges), since the reduction then reads each
+// vertex's partials as one run; part-major when most edges leave a partial.
+bool auto_vmajor(const epk_plan *p) {
+  if (p->kind == EPK_SPMV) return 8 * p->n_slots <= p->m;
+  return p->n_slots > 4 * p->R;
+}
+
 // Algorithmic bytes of one launch under the plan's workspace layout:
 // which = 0 forward part kernel, 1 adjoint part kernel, 2 reduction.  The
 // vertex-major layout adds the slot-index reads to the part kernels; the
@@ -166,7 +176,9 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->geom_ncomp = g->geom_ncomp;
     P->ncls = kind == EPK_SPMV ? 2 : 1;
     P->m = g->n_edges;
-    P->wg = kind == EPK_SPMV ? std::max(64, ((cap + 63) / 64) * 64) : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
+    // SpMV: two edges per lane; FLUX5: one edge per lane up to 256 lanes
+    P->wg = kind == EPK_SPMV ? std::max(64, (((cap + 1) / 2 + 63) / 64) * 64)
+                             : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
     Incidence inc;
     int s = order >= 0 ? run_partition(g, cap, order, P->part, P->task, P->stats, &inc, class_weight, hub_degree)
                        : given_partition(g, given_k, given_part, given_task, P->part, P->task, P->stats, &inc);
@@ -442,7 +454,7 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     }
     P->R = int64_t(rvid.size());
     P->n_slots = int64_t(red_foreign.size());
-    P->vmajor = P->n_slots > 4 * P->R;  // gather-heavy reduction: many slots per vertex
+    P->vmajor = auto_vmajor(P);
     P->n_heavy = int64_t(heavy.size());
     P->n_out = nred;
     P->n_active_out = kind == EPK_SPMV ? active[1] - P->n_x : active[0];
@@ -792,7 +804,7 @@ int epk_plan_set_launch(epk_plan *p, int32_t wg, int32_t xcd_swizzle) {
   if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
   if (wg != 0) {
     if (wg < 64 || wg > 1024 || wg % 64) return epk::fail(EPK_EINVAL, "workgroup must be 64..1024, multiple of 64");
-    if (p->kind == EPK_SPMV && wg < p->cap) return epk::fail(EPK_EINVAL, "SpMV workgroup must be >= capacity");
+    if (p->kind == EPK_SPMV && 4 * wg < p->cap) return epk::fail(EPK_EINVAL, "SpMV needs capacity <= 4 * workgroup");
     if (p->kind == EPK_FLUX5 && p->cap > 8 * wg) return epk::fail(EPK_EINVAL, "FLUX5 needs capacity <= 8 * workgroup");
   }
   if (xcd_swizzle < -1 || xcd_swizzle > 1) return epk::fail(EPK_EINVAL, "xcd_swizzle must be -1, 0 or 1");
@@ -822,7 +834,7 @@ int epk_plan_set_slot_layout(epk_plan *p, int32_t layout) {
   if (!p) return epk::fail(EPK_EINVAL, "plan is NULL");
   if (layout < -1 || layout > 1) return epk::fail(EPK_EINVAL, "layout must be -1, 0 or 1");
   const bool before = p->vmajor;
-  p->vmajor = layout < 0 ? p->n_slots > 4 * p->R : layout == 1;
+  p->vmajor = layout < 0 ? epk::auto_vmajor(p) : layout == 1;
   if (p->kind == EPK_FLUX5 && p->vmajor != before) {
     // the slot indices take LDS in the vertex-major layout: resize, and keep
     // the old layout if the kernels in use would no longer fit

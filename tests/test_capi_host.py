@@ -316,7 +316,9 @@ def test_plan_handles_empty_graph():
 
 
 def test_slot_layout_choice_and_bytes():
-    """Meshes keep the part-major workspace, power-law SpMV takes the vertex-major one.
+    """Meshes keep the part-major workspace; SpMV takes the vertex-major one while its y
+    partials number at most one per eight edges (hub-split EP on R-MAT), part-major above
+    (uniform EP on R-MAT, whose cut falls on the rows).
     Vertex-major: the part kernel reads one slot index per foreign entry (4 C bytes).
     Part-major: the reduction reads a 16-byte record per replicated vertex in place of
     its id and offsets (4 R + 4 (R + 1)); mesh vertices never have more than the
@@ -341,8 +343,19 @@ def test_slot_layout_choice_and_bytes():
         P.set_slot_layout(2)
     R = gen.rmat(scale=12, n_edges=60_000, seed=1)
     g = spmv_graph(R, R["shuffle"])
-    S = Plan(g["edges"], g["n"], 256, g["w"], kind="spmv", n_x=g["n_x"])
-    assert S.info()["vertex_major"] == 1
+    m = len(g["edges"])
+    seen = set()
+    for kw in ({}, {"class_weight": (1, 4), "hub_degree": 16}):
+        S = Plan(g["edges"], g["n"], 256, g["w"], kind="spmv", n_x=g["n_x"], **kw)
+        fo = S.layout()["foreign_offset"]
+        s_y = int(sum(fo[2 * p + 2] - fo[2 * p + 1] for p in range(S.stats["n_parts"])))
+        vm = S.info()["vertex_major"]
+        assert vm == int(8 * s_y <= m), (kw, s_y, m)
+        seen.add(vm)
+        S.set_slot_layout(1 - vm)
+        S.set_slot_layout(-1)
+        assert S.info()["vertex_major"] == vm
+    assert seen == {0, 1}  # both rules' sides are exercised
 
 
 def test_plan_from_caller_partition():
