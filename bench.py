@@ -1062,11 +1062,12 @@ def bench_spmv(args, torch):
                                                  if GRAPH_TIMING else "step: eager launches")
                                       + "; kernels: median of launches timed by their dispatch timestamps"})
     traffic = measured_traffic("rmat20")
+    kern = [v["bytes"] for name, v in (traffic or {}).get(SPMV_HEADLINE, {}).items()
+            if name.startswith({"spmv": "spmv_kernel", "reduce": "reduce_kernel"}[dom])]
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS,
                        "timing": f"median of {args.steps} launches, timed by the dispatch's own timestamps",
-                       "traffic": (traffic[SPMV_HEADLINE][{"spmv": "spmv_kernel", "reduce": "reduce_kernel<1, false>"}[dom]]
-                                   ["bytes"] if traffic and SPMV_HEADLINE in traffic else None)}
+                       "traffic": kern[0] if len(kern) == 1 else None}
     out["orders"] = res
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s, gpu_y)
