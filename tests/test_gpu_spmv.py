@@ -138,3 +138,35 @@ def test_spmv_adjoint_against_oracle(order, cap):
     assert_close(f"spmv-adj/{order}/{cap}/g_x", gx, ref_x, abs_x)
     assert_close(f"spmv-adj/{order}/{cap}/g_w", g_w.cpu().numpy(), ref_w, abs_w)
     assert torch.equal(P.spmv_adjoint(gyp), g_x)  # without the weight gradient: the same g_x, bit for bit
+
+
+@pytest.mark.parametrize("cap,hub", [(256, 0), (256, 16), (128, 0), (1024, 64)])
+def test_spmv_edges_per_lane(cap, hub):
+    """The SpMV kernel with one, two and four edges per lane (workgroups of cap, cap/2 and cap/4
+    lanes) against the oracle: runs of a row inside a lane, across lanes and across wavefronts,
+    on R-MAT rows long enough to span a whole part."""
+    from paper_1605_02043_amd import Plan
+
+    R = gen.rmat(scale=14, n_edges=1 << 18, seed=7)
+    g = spmv_graph(R, R["shuffle"])
+    ref = spmv.forward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    A = spmv.forward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"])
+    P = Plan(g["edges"], g["n"], cap, g["w"], kind="spmv", n_x=g["n_x"], class_weight=(1, 4),
+             hub_degree=hub).upload("cuda")
+    perm = P.perm()
+    n_x = g["n_x"]
+    xp = torch.from_numpy(np.ascontiguousarray(R["x"][perm[:n_x]])).cuda()
+    for ept in (1, 2, 4):
+        wg = max(64, -(-cap // ept))
+        if -(-cap // wg) != ept:
+            continue
+        for layout in (0, 1):
+            say(f"case spmv ept={ept} cap={cap} hub={hub} wg={wg} layout={layout}")
+            P.set_launch(wg)
+            P.set_slot_layout(layout)
+            y = P.spmv(xp)
+            torch.cuda.synchronize()
+            out = np.empty(g["n"] - n_x, dtype=np.float32)
+            out[perm[n_x:] - n_x] = y.cpu().numpy()
+            assert_close(f"spmv14/ept{ept}/{cap}/{hub}/{layout}", out, ref, A)
+            assert torch.equal(P.spmv(xp), y)  # launch after launch: the same bits
