@@ -1057,7 +1057,13 @@ def bench_spmv(args, torch):
             yv = P.spmv(x).cpu().numpy()
             gpu_y = np.empty(R["n_y"], dtype=np.float32)
             gpu_y[perm[R["n_x"]:] - R["n_x"]] = yv
+            # and its adjoint for a seeded g_y, in original column order (compared with the transpose plan)
+            gy_orig = np.random.default_rng(3).standard_normal(R["n_y"]).astype(np.float32)
+            gxv = P.spmv_adjoint(torch.from_numpy(np.ascontiguousarray(gy_orig[perm[R["n_x"]:] - R["n_x"]])).cuda())
+            gx_same = np.empty(R["n_x"], dtype=np.float32)
+            gx_same[perm[:R["n_x"]]] = gxv.cpu().numpy()
         del P
+    res[SPMV_HEADLINE]["adjoint_transpose_plan"] = spmv_adjoint_transpose_plan(args, torch, R, gy_orig, gx_same)
     ep = res[SPMV_HEADLINE]
     dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
     ach = ep["algorithmic_bytes"][dom] / (ep["kernels_ms"][dom] * 1e-3) / 1e9
@@ -1083,6 +1089,44 @@ def bench_spmv(args, torch):
     out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_spmv(R, args.cpu_budget_s, gpu_y)
     print(json.dumps(out), flush=True)
+
+
+def spmv_adjoint_transpose_plan(args, torch, R, gy_orig, gx_same):
+    """g_x = A^T g_y as the forward SpMV of a plan of A^T (the headline order's partition rules
+    applied to the transpose).  The same-plan adjoint scatters into the x class, which R-MAT
+    replicates at almost every nonzero; the transpose plan reduces that class as the forward
+    reduces y.  Returns its time per call (eager, events around K calls), its plan time and its
+    normwise difference from the same-plan adjoint."""
+    from gen.rmat import spmv_graph
+    from paper_1605_02043_amd import Plan
+
+    RT = {"rows": R["cols"], "cols": R["rows"], "w": R["w"], "n_x": R["n_y"], "n_y": R["n_x"]}
+    g = spmv_graph(RT, R["shuffle"])
+    t0 = time.perf_counter()
+    P = Plan(g["edges"], g["n"], args.cap, g["w"], order="ep", kind="spmv", n_x=g["n_x"],
+             class_weight=(1, SPMV_Y_WEIGHT), hub_degree=SPMV_HUB_DEGREE)
+    P.upload("cuda")
+    plan_s = time.perf_counter() - t0
+    perm = P.perm()
+    n_in = g["n_x"]
+    gyp = torch.from_numpy(np.ascontiguousarray(gy_orig[perm[:n_in]])).cuda()
+    for _ in range(args.warmup):
+        gx = P.spmv(gyp)
+    a0, a1 = _ev(torch), _ev(torch)
+    torch.cuda.synchronize()
+    a0.record()
+    for _ in range(args.steps):
+        gx = P.spmv(gyp, out=gx)
+    a1.record()
+    torch.cuda.synchronize()
+    out = np.empty(R["n_x"], dtype=np.float32)
+    out[perm[n_in:] - n_in] = gx.cpu().numpy()
+    diff = float(np.linalg.norm(out.astype(np.float64) - gx_same) / max(np.linalg.norm(gx_same.astype(np.float64)), 1e-300))
+    res = {"ms": a0.elapsed_time(a1) / args.steps, "plan_seconds": plan_s,
+           "normwise_diff_vs_same_plan_adjoint": diff, "loads_per_edge": P.stats["loads"] / len(g["edges"])}
+    print(f"# adjoint by the transpose plan: {res}", file=sys.stderr, flush=True)
+    del P
+    return res
 
 
 def bench_batch(args, torch):
