@@ -110,8 +110,9 @@ def summarize_trace(path: str) -> str:
 
 def summarize_spmv_trace(path: str) -> str:
     """Markdown summary of a rocprofv3 kernel trace (CSV) of `bench.py --workload rmat20`, per task
-    order: the orders run one after another, each after its own partition and plan build, so the
-    library's dispatches split at the len(SPMV_ORDERS) - 1 longest gaps between them."""
+    order: the orders run one after another, each after its own partition and plan build, and the
+    plan of the transpose last, so the library's dispatches split at the len(SPMV_ORDERS) longest
+    gaps between them."""
     import csv
 
     rows = []
@@ -121,10 +122,11 @@ def summarize_spmv_trace(path: str) -> str:
                 rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short_name(r["Kernel_Name"]),
                              int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)))
     rows.sort()
-    gaps = sorted(range(len(rows) - 1), key=lambda i: rows[i][1] - rows[i + 1][0])[:len(SPMV_ORDERS) - 1]
+    phases = SPMV_ORDERS + ("transpose plan (adjoint of " + SPMV_HEADLINE + ")",)
+    gaps = sorted(range(len(rows) - 1), key=lambda i: rows[i][1] - rows[i + 1][0])[:len(phases) - 1]
     cuts = [0] + sorted(i + 1 for i in gaps) + [len(rows)]
     out = ["| order | kernel | workgroups | launches | mean us | median us |", "|---|---|---|---|---|---|"]
-    for order, a, b in zip(SPMV_ORDERS, cuts[:-1], cuts[1:]):
+    for order, a, b in zip(phases, cuts[:-1], cuts[1:]):
         groups = {}
         for t0, t1, name, grid in rows[a:b]:
             groups.setdefault((name, grid), []).append((t1 - t0) / 1e3)
