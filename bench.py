@@ -293,7 +293,8 @@ def spmv_traffic_json(paths) -> dict:
                     acc.setdefault((order, name), {}).setdefault(c, []).append(v)
     out = {"source_sha256": source_sha256(), "workload": "rmat20",
            "counters": "request-size counters per dispatch as for tet55; dispatches split per order by dispatch order",
-           "commands": pmc_commands("rmat20", "--workload rmat20 --steps 3 --warmup 1 --no-cpu-baseline")}
+           "commands": pmc_commands("rmat20", "--workload rmat20 --steps 3 --warmup 1 --no-cpu-baseline "
+                                              "--no-transpose-adjoint")}
     for (order, name), cs in sorted(acc.items()):
         b = _bytes_of({c: float(np.mean(v)) for c, v in cs.items()})
         b["bytes"] = b.get("read_bytes", 0.0) + b.get("write_bytes", 0.0)
@@ -326,6 +327,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-default-order", action="store_true")
     ap.add_argument("--no-baselines", action="store_true", help="skip the random and greedy vertex-cut orders")
+    ap.add_argument("--no-transpose-adjoint", action="store_true",
+                    help="rmat20: skip the adjoint through a plan of the transpose")
     ap.add_argument("--adaptive", type=int, default=0, metavar="STEPS",
                     help="run STEPS forward steps under adaptive overhead control (background partition) and exit")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -1065,7 +1068,8 @@ def bench_spmv(args, torch):
             gx_same = np.empty(R["n_x"], dtype=np.float32)
             gx_same[perm[:R["n_x"]]] = gxv.cpu().numpy()
         del P
-    res[SPMV_HEADLINE]["adjoint_transpose_plan"] = spmv_adjoint_transpose_plan(args, torch, R, gy_orig, gx_same)
+    if not args.no_transpose_adjoint:
+        res[SPMV_HEADLINE]["adjoint_transpose_plan"] = spmv_adjoint_transpose_plan(args, torch, R, gy_orig, gx_same)
     ep = res[SPMV_HEADLINE]
     dom = max(ep["kernels_ms"], key=ep["kernels_ms"].get)
     ach = ep["algorithmic_bytes"][dom] / (ep["kernels_ms"][dom] * 1e-3) / 1e9
