@@ -170,3 +170,34 @@ def test_spmv_edges_per_lane(cap, hub):
             out[perm[n_x:] - n_x] = y.cpu().numpy()
             assert_close(f"spmv14/ept{ept}/{cap}/{hub}/{layout}", out, ref, A)
             assert torch.equal(P.spmv(xp), y)  # launch after launch: the same bits
+
+
+def test_spmv_adjoint_through_transpose_plan():
+    """g_x = A^T g_y as the forward SpMV of a plan of A^T (hub split and weights as the forward's
+    plan) against the oracle's adjoint, and close to the same-plan adjoint."""
+    from paper_1605_02043_amd import Plan
+
+    R = gen.rmat(scale=14, n_edges=1 << 18, seed=9)
+    gy = np.random.default_rng(4).standard_normal(R["n_y"]).astype(np.float32)
+    g = spmv_graph(R, R["shuffle"])
+    ref, _ = spmv.backward(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)
+    A, _ = spmv.backward_abs(R["n_x"], R["n_y"], g["edges"], g["w"], R["x"], gy)
+    RT = {"rows": R["cols"], "cols": R["rows"], "w": R["w"], "n_x": R["n_y"], "n_y": R["n_x"]}
+    gt = spmv_graph(RT, R["shuffle"])
+    say("case spmv adjoint via the transpose plan")
+    PT = Plan(gt["edges"], gt["n"], 256, gt["w"], kind="spmv", n_x=gt["n_x"], class_weight=(1, 4),
+              hub_degree=16).upload("cuda")
+    perm = PT.perm()
+    n_in = gt["n_x"]
+    gx = PT.spmv(torch.from_numpy(np.ascontiguousarray(gy[perm[:n_in]])).cuda())
+    torch.cuda.synchronize()
+    out = np.empty(R["n_x"], dtype=np.float32)
+    out[perm[n_in:] - n_in] = gx.cpu().numpy()
+    assert_close("spmv14/adjoint-by-transpose", out, ref, A)
+    P = Plan(g["edges"], g["n"], 256, g["w"], kind="spmv", n_x=g["n_x"], class_weight=(1, 4),
+             hub_degree=16).upload("cuda")
+    p2 = P.perm()
+    gx2 = P.spmv_adjoint(torch.from_numpy(np.ascontiguousarray(gy[p2[g["n_x"]:] - g["n_x"]])).cuda())
+    same = np.empty(R["n_x"], dtype=np.float32)
+    same[p2[:g["n_x"]]] = gx2.cpu().numpy()
+    assert np.linalg.norm(out.astype(np.float64) - same) <= 1e-5 * np.linalg.norm(same.astype(np.float64))
