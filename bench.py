@@ -935,6 +935,7 @@ def bench_adaptive(args, torch):
     out["adaptive"] = {"decision": ad.decision, "switched_at_step": switched_at, "wall_s": wall,
                        "partition_and_plan_s": info["seconds"], "saving_bound": info["saving_bound"],
                        "step_ms": t, "estimates": est}
+    out["source_sha256"] = source_sha256()
     out["cpu_baseline"] = None
     ad.close()
     print(json.dumps(out), flush=True)
