@@ -257,6 +257,8 @@ int epk_plan_set_staging(epk_plan *p, int32_t staged);
  * with more partials than one thread sums, a part signalling more than 64
  * parts, or arrays beyond 2 GiB.  Host only.                               */
 int epk_plan_set_fused(epk_plan *p, int32_t on);
+/* Frees the plan's host memory (NULL is ignored).  The device image and
+ * workspace belong to the caller and are not touched.                     */
 void epk_plan_destroy(epk_plan *p);
 
 /* ---------------------------------------------------------------- device */
@@ -418,6 +420,8 @@ int epk_batch_info(const epk_batch *b, int64_t *info, int32_t n_info);
 int epk_batch_forward(const epk_batch *b, const float *q, float *r, void *d_ws, void *stream);
 int epk_batch_backward(const epk_batch *b, const float *q, const float *g_r, float *g_q, void *d_ws,
                        void *stream);
+/* Frees the batch's host memory (NULL is ignored); the plans it was merged
+ * from and the caller's device buffers stay as they are.                  */
 void epk_batch_destroy(epk_batch *b);
 
 /* Capacity and launch-shape selection for a batch (the block-size study of
@@ -442,7 +446,11 @@ int epk_autotune(const epk_graph *gs, int32_t n_graphs, const int32_t *caps, int
                  const char *cache_path, void *d_scratch, size_t scratch_bytes, void *stream,
                  int32_t *chosen_cap, int32_t *chosen_wg, int32_t *chosen_direct);
 
+/* Message of the last non-OK status on the calling thread (empty after a
+ * successful call); the string belongs to the library and stays valid until
+ * this thread's next call.                                                */
 const char *epk_last_error(void);
+/* Library name, version and target ("epk 0.1 (gfx950)"); static string.   */
 const char *epk_version(void);
 
 #ifdef __cplusplus
