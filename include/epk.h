@@ -326,6 +326,9 @@ int epk_run_stage(const epk_plan *p, int32_t op, int32_t stage, const float *in,
 int epk_run_stage_timed(const epk_plan *p, int32_t op, int32_t stage, const float *in, const float *g_r, float *out,
                         float dt, float *q_new, void *d_ws, void *stream, float *ms);
 /* op codes of epk_run_stage */
+#define EPK_OP_FORWARD 0
+#define EPK_OP_BACKWARD 1
+#define EPK_OP_SPMV 2
 /* SpMV adjoint on the same plan (Section 5.2's graph, transposed; the
  * paper has no adjoint): g_x = A^T g_y (g_x[j] = sum over the
  * nonzeros (i, j) of w g_y[i]) and, if g_w != NULL, the weight gradient
@@ -338,9 +341,6 @@ int epk_run_stage_timed(const epk_plan *p, int32_t op, int32_t stage, const floa
  * order).                                                                 */
 int epk_spmv_adjoint(const epk_plan *p, const float *x, const float *g_y, float *g_x, float *g_w, void *d_ws,
                      void *stream);
-#define EPK_OP_FORWARD 0
-#define EPK_OP_BACKWARD 1
-#define EPK_OP_SPMV 2
 /* dst[i] = src[idx[i]] (inverse = 0) or dst[idx[i]] = src[i] (inverse = 1),
  * rows of ncomp float32 (device, n_rows rows each; idx device int32
  * [n_rows]); packs states into / out of the packed order, the data layout
