@@ -19,10 +19,12 @@ edges, "least loaded" = fewest edges, then smaller id:
 Tasks inside a part run in ascending edge id.
 
 Greedy is pinned exactly on a hand-derived 9-edge case
-(tests/golden/greedy_vertex_cut9.json).  Parity unpinned beyond that and the
-other pins in the tests (capacity, balance, closed forms, the published
-SplitMix64 outputs): the exact placement is fixed by this specification and
-checked against the library bit for bit.
+(tests/golden/greedy_vertex_cut9.json) that takes each of the four cases
+above (the tie between endpoints is not exercised there), and by
+capacity, balance and closed forms in the tests; random by SplitMix64's
+published outputs.  On larger graphs the exact placement has no value
+independent of these rules; there the library is compared with the oracle bit
+for bit.
 """
 
 from __future__ import annotations
