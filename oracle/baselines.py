@@ -20,7 +20,7 @@ Tasks inside a part run in ascending edge id.
 
 Greedy is pinned exactly on a hand-derived 9-edge case
 (tests/golden/greedy_vertex_cut9.json) that takes each of the four cases
-above (the tie between endpoints is not exercised there), and by
+above, on a 5-edge case where the endpoints tie (greedy_tie5.json), and by
 capacity, balance and closed forms in the tests; random by SplitMix64's
 published outputs.  On larger graphs the exact placement has no value
 independent of these rules; there the library is compared with the oracle bit

@@ -155,10 +155,11 @@ def test_partition_parity_grid64_and_fig1(golden_dir):
     assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"] and st_["n_parts"] == H["k"]
     part, task, _ = partition(E, H["n"], H["capacity"], "ggp")
     assert part.tolist() == H["ggp_parts"] and task.tolist() == H["ggp_task_order"]
-    H = json.load(open(os.path.join(golden_dir, "greedy_vertex_cut9.json")))
-    part, task, st_ = partition(np.array(H["edges"]), H["n"], H["capacity"], "greedy")
-    assert part.tolist() == H["greedy_parts"] and task.tolist() == H["greedy_task_order"]
-    assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"]
+    for name in ("greedy_vertex_cut9.json", "greedy_tie5.json"):
+        H = json.load(open(os.path.join(golden_dir, name)))
+        part, task, st_ = partition(np.array(H["edges"]), H["n"], H["capacity"], "greedy")
+        assert part.tolist() == H["greedy_parts"] and task.tolist() == H["greedy_task_order"]
+        assert st_["loads"] == H["loads"] and st_["cost"] == H["cost"]
     for name in ("multilevel_refine5.json", "multilevel_contiguity6.json"):  # refinement; contiguity
         H = json.load(open(os.path.join(golden_dir, name)))
         E = np.array(H["edges"])

@@ -536,16 +536,18 @@ def test_random_baseline_is_balanced_permutation(m, cap):
     assert (part[task] == np.arange(m) // cap).all()
 
 
-def test_greedy_baseline_hand_derived(golden_dir):
-    """Greedy vertex-cut placement on a 9-edge graph, derived by hand
-    (tests/golden/greedy_vertex_cut9.json): shared part, the endpoint with more unplaced
-    edges, one placed endpoint, and the fall-back to the least loaded part when the preferred
-    parts are full."""
+@pytest.mark.parametrize("name", ["greedy_vertex_cut9.json", "greedy_tie5.json"])
+def test_greedy_baseline_hand_derived(golden_dir, name):
+    """Greedy vertex-cut placement on small graphs derived by hand: a 9-edge graph
+    (greedy_vertex_cut9.json: shared part, the endpoint with more unplaced edges, one placed
+    endpoint, and the fall-back to the least loaded part when the preferred parts are full),
+    and a 5-edge graph whose endpoints tie on unplaced edges (greedy_tie5.json: the first
+    endpoint's parts win)."""
     import json
 
     from oracle.baselines import greedy_partition
 
-    G = json.load(open(os.path.join(golden_dir, "greedy_vertex_cut9.json")))
+    G = json.load(open(os.path.join(golden_dir, name)))
     E = np.array(G["edges"])
     part, task = greedy_partition(E, G["n"], G["capacity"])
     assert part.tolist() == G["greedy_parts"] and task.tolist() == G["greedy_task_order"]
