@@ -166,6 +166,25 @@ def test_single_edge_forward_hand_derived():
     assert np.allclose(r, np.stack([F, -F]), rtol=0, atol=1e-14)
 
 
+# The same edge in 3D, turned so that the normal has a z component and scaled by an area:
+# n = (0, 0.6, -0.8), a = 2, q_u = (1, 0, -1, 2, 3), q_v = (2, 0, 2, -2, 5).  The momenta
+# move with the normal (m2, m3 take the roles of m1, m2 above), so m.n and |m|^2 are as
+# before: s_u = -2.2, p_u = 0.2, s_v = 1.4, p_v = 1.2,
+#   f_u = (-2.2, 0, 2.2 + 0.12, -4.4 - 0.16, -7.04) = (-2.2, 0, 2.32, -4.56, -7.04),
+#   f_v = (2.8, 0, 2.8 + 0.72, -2.8 - 0.96, 8.68) = (2.8, 0, 3.52, -3.76, 8.68),
+#   a [(f_u + f_v)/2 - (q_v - q_u)/2] = 2 [(0.3, 0, 2.92, -4.16, 0.82) - (0.5, 0, 1.5, -2, 1)]
+#     = (-0.4, 0, 2.84, -4.32, -0.36).
+# The area multiplies the dissipation as well as the Euler flux: leaving it off the
+# dissipation would give (0.1, 0, 4.34, -6.32, 0.64).
+
+
+def test_single_edge_3d_with_area_hand_derived():
+    q = np.array([[1.0, 0.0, -1.0, 2.0, 3.0], [2.0, 0.0, 2.0, -2.0, 5.0]])
+    geom = np.array([[0.0, 0.6, -0.8, 2.0]])
+    F = np.array([-0.4, 0.0, 2.84, -4.32, -0.36])
+    assert np.allclose(flux.forward(2, _E1, geom, q), np.stack([F, -F]), rtol=0, atol=1e-14)
+
+
 def test_single_edge_abs_floors_hand_derived():
     """Pins the tolerance floors themselves: a floor that drops a term, keeps a sign or is
     inflated by any factor misses these values (so an elementwise parity check cannot be
