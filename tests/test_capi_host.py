@@ -80,6 +80,20 @@ def test_plan_errors():
     assert e.value.status == _lib.EPK_ERANGE
 
 
+def test_lds_budget_boundary_on_tet32():
+    """tet32 at capacity 896 fits the 64 KiB of LDS a workgroup may ask for (the adjoint's
+    staging takes 99% of it, the GPU case of the largest capacity); at 1024 the plan is
+    refused with EPK_ERANGE before anything touches a device."""
+    import gen
+
+    G = gen.workload("tet32", seed=0)
+    P = Plan(G["edges"], G["n"], 896, G["geom"].astype(np.float32))
+    assert 0.99 * 65536 <= P.info()["lds_bwd"] <= 65536
+    with pytest.raises(_lib.EpkError) as e:
+        Plan(G["edges"], G["n"], 1024, G["geom"].astype(np.float32))
+    assert e.value.status == _lib.EPK_ERANGE and "LDS" in str(e.value)
+
+
 def test_device_calls_refuse_before_upload():
     P = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
     lib = _lib.lib

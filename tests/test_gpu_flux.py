@@ -166,6 +166,38 @@ def test_bitwise_determinism_and_launch_shapes():
         assert torch.equal(r, outs[0][0]) and torch.equal(g, outs[0][1])
 
 
+# The largest capacity at which tet32's adjoint still fits the 64 KiB of LDS a workgroup
+# may ask for (its parts then touch up to 611 vertices; capacity 1024 is refused).
+MAX_CAP_TET32 = 896
+
+
+def test_largest_capacity_that_fits():
+    """A maximum-size case: tet32 at the largest capacity whose adjoint fits the LDS budget
+    (within 1% of it), forward and adjoint against the oracle, and bitwise the same at one,
+    two, four and eight edges per lane."""
+    G = gen.workload("tet32", seed=0)
+    say(f"case largest capacity tet32 cap={MAX_CAP_TET32}")
+    P = _plan(G, MAX_CAP_TET32)
+    info = P.info()
+    assert 0.99 * 65536 <= info["lds_bwd"] <= 65536 and P.stats["max_part_edges"] == MAX_CAP_TET32
+    q = gen.flux_state(G["n"], seed=0)
+    gr = gen.workloads.grad_seed(G["n"], seed=0)
+    g = _geom32(G)
+    assert_close("maxcap/r", _fwd(P, q), flux.forward(G["n"], G["edges"], g, q), flux.forward_abs(G["n"], G["edges"], g, q))
+    assert_close("maxcap/g_q", _bwd(P, q, gr), flux.backward(G["n"], G["edges"], g, q, gr),
+                 flux.backward_abs(G["n"], G["edges"], g, q, gr))
+    perm = P.perm()
+    qd = torch.from_numpy(pack_rows(q, perm)).cuda()
+    gd = torch.from_numpy(pack_rows(gr, perm)).cuda()
+    outs = []
+    for wg in (1024, 512, 256, 128):
+        say(f"  wg={wg}")
+        P.set_launch(wg, 1)
+        outs.append((P.forward(qd).cpu(), P.backward(qd, gd).cpu()))
+    for r, gq in outs[1:]:
+        assert torch.equal(r, outs[0][0]) and torch.equal(gq, outs[0][1])
+
+
 def test_orders_agree():
     G = gen.workload("tet32", seed=2)
     q = gen.flux_state(G["n"], seed=2)
