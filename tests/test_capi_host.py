@@ -94,6 +94,48 @@ def test_lds_budget_boundary_on_tet32():
     assert e.value.status == _lib.EPK_ERANGE and "LDS" in str(e.value)
 
 
+@pytest.mark.parametrize("name,order,layout", [("tet", "ep", 0), ("tet", "ep", 1), ("tet", "input", 0),
+                                               ("grid", "ep", 1), ("grid", "input", 0)])
+def test_algorithmic_bytes_recounted(name, order, layout):
+    """The roofline's numerators (epk_plan_info's algorithmic bytes), recounted here from the
+    partition alone (loads, cost, replication from the oracle's cost function) with the bytes
+    each kernel must move: the part kernels' edge records (4 + 4g per edge, g = 3 for the 3D
+    area vector, 2 for the 2D normal), incidence lists (4 per edge), offsets (2 per local
+    vertex and one more, each part's list padded to an even count), foreign ids (4 C), state
+    gathers (20 L, 40 L for the adjoint's two row sets), owned rows (20 n_active) and partials
+    (20 C), plus 32 bytes of header per part; the reduction's ids, offsets or records, partials
+    and owner rows, and the zeroed untouched vertices."""
+    import gen
+    from oracle import cost
+
+    G = gen.tet_mesh(6, 5, 4, seed=3) if name == "tet" else gen.workload("grid64", seed=1)
+    E = np.asarray(G["edges"])
+    n, m = G["n"], len(E)
+    P = Plan(E, n, 64, G["geom"].astype(np.float32), order=order)
+    P.set_slot_layout(layout)
+    info, st, lay = P.info(), P.stats, P.layout()
+    part, _ = P.part_of_edge()
+    k = st["n_parts"]
+    c = cost.partition_cost(E, n, part, k)
+    L, C, R, na = c["loads"], c["cost"], c["replicated"], c["n_active"]
+    assert (L, C, R) == (st["loads"], st["cost"], st["replicated"])
+    U = lay["own_count"][:, 0].astype(np.int64) + np.diff(lay["foreign_offset"])
+    assert U.sum() == L
+    nloff = int(np.sum((U + 2) & ~1))
+    g = 3 if G["geom"].shape[1] == 4 else 2
+    meta = 32 * k + 4 * m + 4 * g * m + 4 * m + 2 * nloff + 4 * C
+    ids = 4 * C if layout == 1 else 0
+    fwd_kernel = meta + 20 * L + 20 * na + 20 * C + ids
+    bwd_kernel = meta + 40 * L + 20 * na + 20 * C + ids
+    red = 4 * R + 4 * (R + 1) + 20 * C + 40 * R + 20 * (n - na)
+    if layout == 0:  # a 16-byte record per replicated vertex replaces its id and offsets
+        ns = c["p_v"][c["p_v"] >= 2] - 1
+        red += 16 * R - 4 * R - 4 * (R + 1) + int(np.sum(8 + 4 * ns[ns > 3]))
+    assert info["vertex_major"] == layout
+    assert (info["bytes_fwd_kernel"], info["bytes_bwd_kernel"]) == (fwd_kernel, bwd_kernel)
+    assert (info["bytes_fwd"], info["bytes_bwd"]) == (fwd_kernel + red, bwd_kernel + red)
+
+
 def test_device_calls_refuse_before_upload():
     P = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
     lib = _lib.lib
