@@ -136,6 +136,40 @@ def test_algorithmic_bytes_recounted(name, order, layout):
     assert (info["bytes_fwd"], info["bytes_bwd"]) == (fwd_kernel + red, bwd_kernel + red)
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_spmv_algorithmic_bytes_recounted(layout):
+    """The same for SpMV: the part kernel reads 8 bytes per nonzero, 4 per foreign x id and per
+    x load, writes 4 per active y (its owner's partial or its value) and per y partial; the
+    reduction reads ids and offsets (or records), partials and owner values and writes the
+    results, and zeroes the untouched y."""
+    import gen
+    from gen.rmat import spmv_graph
+    from oracle import cost
+
+    R_ = gen.rmat(scale=10, n_edges=1 << 13, seed=4)
+    g = spmv_graph(R_, R_["shuffle"])
+    E, n, n_x, m = np.asarray(g["edges"]), g["n"], g["n_x"], len(g["edges"])
+    P = Plan(E, n, 64, g["w"], kind="spmv", n_x=n_x, class_weight=(1, 4), hub_degree=8)
+    P.set_slot_layout(layout)
+    info, st, lay = P.info(), P.stats, P.layout()
+    part, _ = P.part_of_edge()
+    k = st["n_parts"]
+    pv = cost.partition_cost(E, n, part, k)["p_v"]
+    fo = np.diff(lay["foreign_offset"]).reshape(k, 2)
+    Cx, Cy = int(fo[:, 0].sum()), int(fo[:, 1].sum())
+    Lx = int(lay["own_count"][:, 0].sum()) + Cx
+    py = pv[n_x:]
+    R, na = int(np.sum(py >= 2)), int(np.sum(py >= 1))
+    assert Cy == int(np.sum(py[py >= 2] - 1))
+    kernel = 32 * k + 8 * m + 4 * Cx + 4 * Lx + 4 * na + 4 * Cy + (4 * Cy if layout == 1 else 0)
+    red = 4 * R + 4 * (R + 1) + 4 * Cy + 8 * R + 4 * (n - n_x - na)
+    if layout == 0:
+        ns = py[py >= 2] - 1
+        red += 16 * R - 4 * R - 4 * (R + 1) + int(np.sum(8 + 4 * ns[ns > 3]))
+    assert info["vertex_major"] == layout
+    assert info["bytes_fwd_kernel"] == kernel and info["bytes_fwd"] == kernel + red
+
+
 def test_device_calls_refuse_before_upload():
     P = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
     lib = _lib.lib
