@@ -204,7 +204,7 @@ int epk_plan_info(const epk_plan *p, int64_t *info, int32_t n_info);
 /* Launch shape for later calls: workgroup size wg (64..1024, multiple of
  * 64; FLUX5 requires capacity <= 8 wg, SPMV capacity <= 4 wg: each
  * lane then takes ceil(capacity / wg) consecutive edges of its part (the
- * SpMV default is two; the SpMV adjoint always runs one edge per lane);
+ * SpMV default is four; the SpMV adjoint always runs one edge per lane);
  * 0 keeps the current one) and
  * xcd_swizzle (1: XCD x runs the consecutive parts [x*ceil(k/8),
  * (x+1)*ceil(k/8)), so parts sharing vertices share an L2; 0: part =

@@ -205,6 +205,20 @@ __device__ __forceinline__ void dma_rows2(float *dst0, const float *__restrict__
   }
 }
 
+// dma_block with 16-byte direct-to-LDS loads (gfx950): in each step a wave
+// copies 64 chunks of four dwords, lane l's chunk to (wave base + 16 l bytes);
+// the last n mod 4 dwords go as single dwords.  Sources and destinations need
+// only 4-byte alignment.  A quarter of the load instructions, which matters
+// where the address units bound a kernel (SpMV).
+__device__ __forceinline__ void dma_block16(float *dst, const float *src, int n, int tid, int nt) {
+  const int lane = tid & 63;
+  const int n4 = n & ~3;
+  for (int b = 4 * wave_first(tid); b < n4; b += 4 * nt)
+    if (b + 4 * lane < n4) __builtin_amdgcn_global_load_lds(src + b + 4 * lane, EPK_LDS(dst + b), 16, 0, 0);
+  for (int b = n4 + wave_first(tid); b < n; b += nt)
+    if (b + lane < n) __builtin_amdgcn_global_load_lds(src + b + lane, EPK_LDS(dst + b), 4, 0, 0);
+}
+
 __device__ __forceinline__ void wait_staged() {
   __builtin_amdgcn_s_waitcnt(0);  // all direct-to-LDS loads of this wave have landed
   __syncthreads();
@@ -1300,24 +1314,41 @@ __global__ void __launch_bounds__(1024) spmv_kernel(DevPlan P, const float *__re
 
   // batch 1, all addressed from the part index: header, edge count, foreign x
   // ids (fixed-stride copy) and edge records (part p's at p cap, zero past its
-  // count; positions past the capacity re-read the last record)
+  // count; positions past the capacity re-read the last record).  The kernel
+  // is bound by its address units (one cache line per x gather), so the other
+  // loads take as few instructions as they can: the ids in 16-byte chunks, a
+  // lane's EPT records and weights as one vector load each, and the record
+  // after a wave's last only in its last lane, the one lane that uses it.
   const int4 *h4 = reinterpret_cast<const int4 *>(P.hdr + int64_t(part) * kHdrInts);
   const int4 ha = h4[0], hb = h4[1];
   const int ne = int(P.eoff[part + 1] - P.eoff[part]);
-  dma_block(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
-            P.max_nf, tid, nt);
+  dma_block16(reinterpret_cast<float *>(xid), reinterpret_cast<const float *>(P.pfid) + int64_t(part) * P.max_nf,
+              P.max_nf, tid, nt);
   const uint32_t *el = P.eloc + int64_t(part) * P.cap;
   const float *eg = P.geom + int64_t(part) * P.cap;
   const int j0 = tid * EPT;
   uint32_t w[EPT];
   float wt[EPT];
+  if (EPT > 1 && P.cap % EPT == 0 && j0 + EPT <= P.cap) {  // aligned, inside the block
+    typedef uint32_t vu __attribute__((ext_vector_type(EPT)));
+    typedef float vf __attribute__((ext_vector_type(EPT)));
+    const vu a = *reinterpret_cast<const vu *>(el + j0);
+    const vf b = *reinterpret_cast<const vf *>(eg + j0);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int j = min(j0 + i, P.cap - 1);
-    w[i] = el[j];
-    wt[i] = eg[j];
+    for (int i = 0; i < EPT; ++i) {
+      w[i] = a[i];
+      wt[i] = b[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int j = min(j0 + i, P.cap - 1);
+      w[i] = el[j];
+      wt[i] = eg[j];
+    }
   }
-  const uint32_t w_next = el[min(j0 + EPT, P.cap - 1)];
+  uint32_t w_next = 0;
+  if (lane == 63) w_next = el[min(j0 + EPT, P.cap - 1)];
   wait_staged();
   const int xo = ha.x, xn = ha.y, xnf = ha.w, yo = hb.x, yn = hb.y, yf0 = hb.z, ynf = hb.w;
   // batch 2: owned x block, foreign x values by id, slot indices of the foreign y

@@ -176,8 +176,8 @@ epk_plan *plan_build(const epk_graph *g, int32_t cap, int32_t order, int32_t kin
     P->geom_ncomp = g->geom_ncomp;
     P->ncls = kind == EPK_SPMV ? 2 : 1;
     P->m = g->n_edges;
-    // SpMV: two edges per lane; FLUX5: one edge per lane up to 256 lanes
-    P->wg = kind == EPK_SPMV ? std::max(64, (((cap + 1) / 2 + 63) / 64) * 64)
+    // SpMV: four edges per lane; FLUX5: one edge per lane up to 256 lanes
+    P->wg = kind == EPK_SPMV ? std::max(64, (((cap + 3) / 4 + 63) / 64) * 64)
                              : std::min(256, std::max(64, ((cap + 63) / 64) * 64));
     Incidence inc;
     int s = order >= 0 ? run_partition(g, cap, order, P->part, P->task, P->stats, &inc, class_weight, hub_degree)
