@@ -170,6 +170,15 @@ def test_spmv_algorithmic_bytes_recounted(layout):
     assert info["bytes_fwd_kernel"] == kernel and info["bytes_fwd"] == kernel + red
 
 
+@pytest.mark.parametrize("cap,wg", [(1, 64), (64, 64), (128, 64), (256, 64), (300, 128), (1024, 256)])
+def test_spmv_default_launch_four_edges_per_lane(cap, wg):
+    """SpMV plans launch ceil(capacity / 4) lanes by default, rounded up to whole wavefronts:
+    four edges per lane, the fastest shape on rmat20 once the kernel's loads are vectorised."""
+    E = np.array([[j % 7, 7 + (j * 3) % 11] for j in range(40)], dtype=np.int32)
+    P = Plan(E, 18, cap, np.ones(len(E), np.float32), kind="spmv", n_x=7)
+    assert P.info()["wg"] == wg
+
+
 def test_device_calls_refuse_before_upload():
     P = Plan(np.array([[0, 1], [1, 2]]), 3, 4, np.zeros((2, 4), np.float32))
     lib = _lib.lib
